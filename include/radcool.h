@@ -1,0 +1,209 @@
+/*
+ * radcool.h - C ABI of the MI355X (gfx950) two-temperature radiative cooling
+ * source step.
+ *
+ * The operation (paper "Black hole spectral states revealed in GRMHD
+ * simulations with texture memory accelerated cooling", arXiv:2505.08855):
+ * for every cell of a GRMHD grid, given the electron density n_e [cm^-3], the
+ * electron and ion temperatures T_e, T_i [K], the field strength |B| [G] and
+ * the thermal scale height H [cm] (Sections II.F and II.G list the cell
+ * parameters), read the cooling and Coulomb rates from log-spaced tables by
+ * multilinear interpolation (Section III.A), bridge the optically thin cooling
+ * to the thick limit (Section II.D, eq. total_cooling) and update the electron
+ * and ion internal energies over dt (Section III.B.1), implicitly (backward
+ * Euler, solved by Newton) or explicitly (16 substeps, 30 % limiter), with the
+ * temperature floor of Section III.B.2.
+ *
+ * Conventions shared by every entry point:
+ *   - All functions return rc_status: RC_OK (0) or a negative error code; they
+ *     never abort.  On error, rc_last_error() returns a message (thread-local,
+ *     valid until the next call on the same thread).
+ *   - Arguments that can be checked on the host are checked before anything is
+ *     launched: NULL required pointers, negative sizes, dt <= 0 or not finite,
+ *     malformed table specs give RC_EINVAL and nothing runs.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *     Step and backward calls are asynchronous on that stream and never
+ *     synchronise it; table build, import, export and file I/O are synchronous.
+ *   - Per-cell arrays are device pointers to contiguous FP64 arrays of length
+ *     n (8-byte aligned; 256-byte alignment gives full-speed loads), owned by
+ *     the caller.  Output arrays may not alias inputs.
+ *   - Per-cell problems are not errors: they set bits in the status byte and
+ *     leave the outputs defined (see RC_ST_*).
+ *   - Units are cgs throughout.
+ */
+#ifndef RADCOOL_H
+#define RADCOOL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RC_OK = 0,
+  RC_EINVAL = -1,        /* bad argument (host-detectable) */
+  RC_ENOMEM = -2,        /* device or host allocation failed */
+  RC_EDEVICE = -3,       /* a HIP call failed; message has hipGetErrorString */
+  RC_EUNSUPPORTED = -4,  /* valid request this build or device cannot serve */
+  RC_ESTATE = -5,        /* object in the wrong state (e.g. destroyed handle) */
+  RC_EIO = -6            /* file read/write failed or file malformed */
+} rc_status;
+
+/* Table identifiers and their content (values stored as log2):
+ *   RC_TAB_BREM  log2(N^2 f_brem(theta_e)),     N = n_e H  (Sec. II.A)
+ *   RC_TAB_SYNCH log2 Q_syn(N, T_e, B, H = 1cm)            (Sec. II.B, eq. synchrotron)
+ *   RC_TAB_ETA   log2 eta_comp(nu_c) at H = 1cm            (Sec. II.C)
+ *   RC_TAB_COUL  log2(Q_cc / (T_i - T_e))                  (Sec. II.G, eq. coulomb_collisions)
+ * The three cooling tables share the axes (log10 N, log10 T_e, log10 B); the
+ * Coulomb table has the axes (log10 n_e, log10 T_e, log10 T_i).  The paper's
+ * 4-D cooling table over (H, B, n_e, T_e) reduces exactly to these 3-D tables:
+ * every rate depends on n_e and H only through N = n_e H apart from explicit
+ * powers of H (Q_brem = v_brem / H^2, Q_syn = v_synch / H, eta = v_eta). */
+enum { RC_TAB_BREM = 0, RC_TAB_SYNCH = 1, RC_TAB_ETA = 2, RC_TAB_COUL = 3, RC_NUM_TABLES = 4 };
+
+/* Per-cell status bits (uint8). */
+enum {
+  RC_ST_INVALID = 1,     /* an input was not finite or <= 0: T' = NaN, rates = NaN */
+  RC_ST_CLAMP_COOL = 2,  /* a cooling-table coordinate of the input state was out of range (clamped) */
+  RC_ST_CLAMP_COUL = 4,  /* a Coulomb-table coordinate of the input state was out of range (clamped) */
+  RC_ST_FLOOR = 8,       /* the implicit update ended on the temperature floor */
+  RC_ST_MAXITER = 16     /* the solver hit max_iter; outputs are the best bracketed iterate */
+};
+
+/* One table's three axes, log10-spaced: node k of axis a is
+ * lo[a] + k (hi[a] - lo[a]) / (n[a] - 1), k = 0 .. n[a]-1.  n[a] >= 2, lo < hi. */
+typedef struct {
+  int32_t n[3];
+  double lo[3];
+  double hi[3];
+} rc_axes;
+
+typedef struct {
+  rc_axes cool;          /* log10 N [cm^-2], log10 T_e [K], log10 B [G] */
+  rc_axes coul;          /* log10 n_e [cm^-3], log10 T_e [K], log10 T_i [K] */
+  double ln_lambda;      /* Coulomb logarithm, Sec. II.G (default 20) */
+} rc_table_spec;
+
+typedef struct rc_tables_s* rc_tables;   /* opaque, library-owned device tables */
+
+/* Per-cell input state: device pointers, FP64, length n. */
+typedef struct {
+  const double* n_e;
+  const double* T_e;
+  const double* T_i;
+  const double* B;
+  const double* H;
+} rc_state;
+
+/* Per-cell outputs: device pointers, length n; NULL = not written.
+ * Rates are reported at the INPUT state (the paper's cooling function);
+ * Q_rad is zero when T_e < T_floor.  The effective applied cooling is
+ * (u - u') / dt. */
+typedef struct {
+  double* T_e_new;
+  double* T_i_new;
+  double* Q_rad;         /* bridged radiative cooling, erg cm^-3 s^-1 */
+  double* Q_cc;          /* Coulomb exchange, > 0 when ions heat electrons */
+  uint8_t* status;       /* RC_ST_* bits */
+  double* Q_brem;        /* optional diagnostics */
+  double* Q_syn;
+  double* eta;
+} rc_out;
+
+enum { RC_SCHEME_NEWTON = 0, RC_SCHEME_EXPLICIT16 = 1, RC_SCHEME_RATES = 2 };
+enum { RC_VARIANT_AUTO = 0, RC_VARIANT_GLOBAL = 1, RC_VARIANT_LDS = 2, RC_VARIANT_TEX = 3, RC_VARIANT_DIRECT = 4 };
+
+typedef struct {
+  int32_t scheme;        /* RC_SCHEME_*: backward Euler (Newton), 16-substep explicit, or rates only */
+  int32_t variant;       /* RC_VARIANT_*: how tables are read; DIRECT evaluates closed forms (no tables) */
+  int32_t max_iter;      /* Newton iteration cap (default 60) */
+  int32_t block;         /* threads per workgroup, 0 = library choice */
+  double T_floor;        /* K, cooling is zero below it (Sec. III.B.2; default 1e6) */
+  double tol;            /* target relative accuracy of T_e' (default 1e-12): a Newton step
+                            below sqrt(tol) in ln T_e' ends the solve */
+} rc_step_opts;
+
+/* Fill *spec with the default axes (n points per axis):
+ *   cooling: log10 N in [15, 29], log10 T_e in [5.95, 12.05], log10 B in [-0.5, 10.5]
+ *   Coulomb: log10 n_e in [9.5, 20.5], log10 T_e in [5.95, 12.05], log10 T_i in [5.95, 14.05]
+ * and ln_lambda = 20.  Returns RC_EINVAL for spec == NULL or n < 2. */
+rc_status rc_default_spec(rc_table_spec* spec, int32_t n);
+
+/* Fill *opts with: Newton scheme, AUTO variant, max_iter 60, block 0,
+ * T_floor 1e6 K, tol 1e-12. */
+rc_status rc_default_opts(rc_step_opts* opts);
+
+/* Build the four tables on the current device from the closed forms of Sec. II
+ * (node values in FP64 on the GPU; a least-squares affine function of the node
+ * indices is removed from each log2 table on the host and the residual is
+ * stored in FP32).  Synchronous.  *out receives a new handle owned by the
+ * caller (release with rc_tables_destroy). */
+rc_status rc_build_tables(const rc_table_spec* spec, void* stream, rc_tables* out);
+
+/* Create tables from host data in the storage form: resid holds the FP32
+ * residuals of the four tables back to back, each C-ordered [i0][i1][i2] over
+ * its axes (three cooling tables of n0*n1*n2 values, then the Coulomb table),
+ * and coeffs holds 4 x 4 FP64 affine coefficients (c0, c1, c2, c3 per table,
+ * value = c0 + c1 i0 + c2 i1 + c3 i2 + resid).  Synchronous; host buffers are
+ * only read during the call. */
+rc_status rc_tables_import(const rc_table_spec* spec, const float* resid, const double* coeffs,
+                           void* stream, rc_tables* out);
+
+/* Copy the storage form out to host buffers laid out as in rc_tables_import
+ * (either pointer may be NULL).  Synchronous. */
+rc_status rc_tables_export(rc_tables t, float* resid, double* coeffs);
+
+/* Spec of a table set and the number of residual values (sum over the four tables). */
+rc_status rc_tables_info(rc_tables t, rc_table_spec* spec, int64_t* n_values);
+
+/* Save to / load from a binary file: header (magic, version, spec), the
+ * coefficients, the residuals and a 64-bit checksum of the payload.  Load
+ * verifies the checksum (RC_EIO on mismatch). */
+rc_status rc_tables_save(rc_tables t, const char* path);
+rc_status rc_tables_load(const char* path, void* stream, rc_tables* out);
+
+rc_status rc_tables_destroy(rc_tables t);
+
+/* One cooling source step over n cells (Sec. III.B): rates at the input state
+ * and, unless scheme == RC_SCHEME_RATES, the updated temperatures.  n == 0 is
+ * a no-op.  Asynchronous on stream. */
+rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n, double dt,
+                       const rc_step_opts* opts, const rc_out* out, void* stream);
+
+/* The physical constants compiled into the library, in this order:
+ * c, k_B, h, m_e, m_p, e, sigma_T, sigma_SB; returns how many were written
+ * (at most n). */
+int32_t rc_constants(double* out, int32_t n);
+
+/* Host-side self-test of the node evaluator: evaluates table `table` at node
+ * (i0, i1, i2) of spec on the host CPU with the same source the GPU kernels
+ * are compiled from, writing the log2 value to *value.  For tests only; no
+ * step entry point ever calls it. */
+rc_status rc_selftest_node_host(const rc_table_spec* spec, int32_t table, int32_t i0, int32_t i1,
+                                int32_t i2, double* value);
+
+/* Host-side self-test of special functions (same source as the device code):
+ * which = 0,1,2: exponentially scaled K_nu(x) for nu = which;
+ * which = 3: the synchrotron tail integral J(x) = int_x^inf s I'(s) ds;
+ * which = 4: x_c solving ln(I'(x)/x) = x (input is the log right side).
+ * For tests only. */
+rc_status rc_selftest_special_host(int32_t which, const double* x, double* y, int64_t n);
+
+/* Host-side self-test of the per-cell step (same source as the GPU kernel)
+ * on tables given in the storage form of rc_tables_import (host memory):
+ * host arrays of length n.  For tests only. */
+rc_status rc_selftest_step_host(const rc_table_spec* spec, const float* resid, const double* coeffs,
+                                const double* n_e, const double* T_e, const double* T_i,
+                                const double* B, const double* H, int64_t n, double dt,
+                                const rc_step_opts* opts, double* T_e_new, double* T_i_new,
+                                double* Q_rad, double* Q_cc, uint8_t* status);
+
+/* Message of the last error on this thread ("" if none). */
+const char* rc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RADCOOL_H */

@@ -1,0 +1,295 @@
+"""ctypes binding of libradcool.so (include/radcool.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Device buffers are torch tensors on the current HIP device (torch is
+used for allocation and streams, nothing else).  A missing or unbuilt library
+raises ``RadcoolError``; there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libradcool.so")
+
+RC_OK = 0
+STATUS_NAMES = {-1: "RC_EINVAL", -2: "RC_ENOMEM", -3: "RC_EDEVICE", -4: "RC_EUNSUPPORTED",
+                -5: "RC_ESTATE", -6: "RC_EIO"}
+
+TAB_BREM, TAB_SYNCH, TAB_ETA, TAB_COUL = 0, 1, 2, 3
+ST_INVALID, ST_CLAMP_COOL, ST_CLAMP_COUL, ST_FLOOR, ST_MAXITER = 1, 2, 4, 8, 16
+SCHEME_NEWTON, SCHEME_EXPLICIT16, SCHEME_RATES = 0, 1, 2
+VARIANT_AUTO, VARIANT_GLOBAL, VARIANT_LDS, VARIANT_TEX, VARIANT_DIRECT = 0, 1, 2, 3, 4
+VARIANTS = {"auto": 0, "global": 1, "lds": 2, "tex": 3, "direct": 4}
+SCHEMES = {"newton": 0, "explicit16": 1, "rates": 2}
+
+EXPORTED = ("rc_default_spec", "rc_default_opts", "rc_build_tables", "rc_tables_import",
+            "rc_tables_export", "rc_tables_info", "rc_tables_save", "rc_tables_load",
+            "rc_tables_destroy", "rc_cool_step", "rc_constants", "rc_selftest_node_host",
+            "rc_selftest_special_host", "rc_selftest_step_host", "rc_last_error")
+
+
+class RadcoolError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+class Axes(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
+class TableSpec(ctypes.Structure):
+    _fields_ = [("cool", Axes), ("coul", Axes), ("ln_lambda", ctypes.c_double)]
+
+
+class State(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in ("n_e", "T_e", "T_i", "B", "H")]
+
+
+class Out(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in ("T_e_new", "T_i_new", "Q_rad", "Q_cc", "status",
+                                               "Q_brem", "Q_syn", "eta")]
+
+
+class StepOpts(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int32), ("variant", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("T_floor", ctypes.c_double), ("tol", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Open libradcool.so (once).  Raises RadcoolError if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RadcoolError(-4, "libradcool.so is not built; run python -m paper_2505_08855_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        P = ctypes.POINTER
+        sig = {
+            "rc_default_spec": (i32, [P(TableSpec), i32]),
+            "rc_default_opts": (i32, [P(StepOpts)]),
+            "rc_build_tables": (i32, [P(TableSpec), vp, P(vp)]),
+            "rc_tables_import": (i32, [P(TableSpec), vp, vp, vp, P(vp)]),
+            "rc_tables_export": (i32, [vp, vp, vp]),
+            "rc_tables_info": (i32, [vp, P(TableSpec), P(i64)]),
+            "rc_tables_save": (i32, [vp, ctypes.c_char_p]),
+            "rc_tables_load": (i32, [ctypes.c_char_p, vp, P(vp)]),
+            "rc_tables_destroy": (i32, [vp]),
+            "rc_cool_step": (i32, [vp, P(State), i64, dbl, P(StepOpts), P(Out), vp]),
+            "rc_constants": (i32, [vp, i32]),
+            "rc_selftest_node_host": (i32, [P(TableSpec), i32, i32, i32, i32, P(dbl)]),
+            "rc_selftest_special_host": (i32, [i32, vp, vp, i64]),
+            "rc_selftest_step_host": (i32, [P(TableSpec), vp, vp, vp, vp, vp, vp, vp, i64, dbl,
+                                            P(StepOpts), vp, vp, vp, vp, vp]),
+            "rc_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(code):
+    if code != RC_OK:
+        raise RadcoolError(code, lib().rc_last_error().decode())
+
+
+def default_spec(n=64):
+    s = TableSpec()
+    check(lib().rc_default_spec(ctypes.byref(s), n))
+    return s
+
+
+def spec_from_axes(cool, coul, ln_lambda=20.0):
+    """Build a TableSpec from two sequences of (n, lo, hi) triples."""
+    s = TableSpec()
+    for dst, src in ((s.cool, cool), (s.coul, coul)):
+        for k, (n, lo, hi) in enumerate(src):
+            dst.n[k] = int(n)
+            dst.lo[k] = float(lo)
+            dst.hi[k] = float(hi)
+    s.ln_lambda = ln_lambda
+    return s
+
+
+def default_opts(**kw):
+    o = StepOpts()
+    check(lib().rc_default_opts(ctypes.byref(o)))
+    for k, v in kw.items():
+        if k == "scheme" and isinstance(v, str):
+            v = SCHEMES[v]
+        if k == "variant" and isinstance(v, str):
+            v = VARIANTS[v]
+        setattr(o, k, v)
+    return o
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def spec_sizes(spec):
+    vc = spec.cool.n[0] * spec.cool.n[1] * spec.cool.n[2]
+    vk = spec.coul.n[0] * spec.coul.n[1] * spec.coul.n[2]
+    return vc, vk
+
+
+class Tables:
+    """Owning wrapper of an rc_tables handle."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RadcoolError(-5, "tables already destroyed")
+        return self._h
+
+    @staticmethod
+    def build(spec=None, stream=None):
+        spec = spec if spec is not None else default_spec()
+        h = ctypes.c_void_p()
+        check(lib().rc_build_tables(ctypes.byref(spec), _stream_ptr(stream), ctypes.byref(h)))
+        return Tables(h.value)
+
+    @staticmethod
+    def from_storage(spec, resid, coeffs, stream=None):
+        """Create tables from host FP32 residuals (all four tables back to back) and
+        FP64 coefficients (4 x 4)."""
+        resid = np.ascontiguousarray(resid, dtype=np.float32).ravel()
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.float64).ravel()
+        vc, vk = spec_sizes(spec)
+        if resid.size != 3 * vc + vk or coeffs.size != 16:
+            raise ValueError("storage arrays do not match the spec")
+        h = ctypes.c_void_p()
+        check(lib().rc_tables_import(ctypes.byref(spec), resid.ctypes.data_as(ctypes.c_void_p),
+                                     coeffs.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream),
+                                     ctypes.byref(h)))
+        return Tables(h.value)
+
+    @staticmethod
+    def load(path, stream=None):
+        h = ctypes.c_void_p()
+        check(lib().rc_tables_load(path.encode(), _stream_ptr(stream), ctypes.byref(h)))
+        return Tables(h.value)
+
+    def save(self, path):
+        check(lib().rc_tables_save(self.handle, path.encode()))
+
+    def info(self):
+        spec = TableSpec()
+        n = ctypes.c_int64()
+        check(lib().rc_tables_info(self.handle, ctypes.byref(spec), ctypes.byref(n)))
+        return spec, n.value
+
+    def export(self):
+        """(resid float32 [3*vc + vk], coeffs float64 [4, 4]) on the host."""
+        spec, n = self.info()
+        resid = np.empty(n, dtype=np.float32)
+        coeffs = np.empty(16, dtype=np.float64)
+        check(lib().rc_tables_export(self.handle, resid.ctypes.data_as(ctypes.c_void_p),
+                                     coeffs.ctypes.data_as(ctypes.c_void_p)))
+        return resid, coeffs.reshape(4, 4)
+
+    def destroy(self):
+        if self._h:
+            lib().rc_tables_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()
+
+
+def _check_state(state):
+    import torch
+    ref = state["n_e"]
+    for k in ("n_e", "T_e", "T_i", "B", "H"):
+        t = state[k]
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != ref.numel():
+            raise ValueError("state field %s must be a contiguous float64 HIP tensor of equal length" % k)
+    return ref.numel()
+
+
+def cool_step(tables, state, dt, opts=None, out=None, diagnostics=False, stream=None):
+    """One cooling step.  ``state``: dict of float64 device tensors n_e, T_e, T_i, B, H.
+
+    Returns a dict of output tensors (allocated here unless ``out`` supplies them):
+    T_e_new, T_i_new, Q_rad, Q_cc, status (+ Q_brem, Q_syn, eta with diagnostics).
+    """
+    import torch
+    n = _check_state(state)
+    opts = opts or default_opts()
+    dev = state["n_e"].device
+    if out is None:
+        out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")}
+        out["status"] = torch.empty(n, dtype=torch.uint8, device=dev)
+        if diagnostics:
+            for k in ("Q_brem", "Q_syn", "eta"):
+                out[k] = torch.empty(n, dtype=torch.float64, device=dev)
+    st = State(*[state[k].data_ptr() for k in ("n_e", "T_e", "T_i", "B", "H")])
+    o = Out(*[out[k].data_ptr() if out.get(k) is not None else None
+              for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc", "status", "Q_brem", "Q_syn", "eta")])
+    check(lib().rc_cool_step(tables.handle, ctypes.byref(st), n, float(dt), ctypes.byref(opts),
+                             ctypes.byref(o), _stream_ptr(stream)))
+    return out
+
+
+def constants():
+    buf = (ctypes.c_double * 8)()
+    m = lib().rc_constants(buf, 8)
+    return list(buf)[:m]
+
+
+# ---------------------------------------------------------------- host self-tests
+
+
+def selftest_node_host(spec, table, i0, i1, i2):
+    v = ctypes.c_double()
+    check(lib().rc_selftest_node_host(ctypes.byref(spec), table, i0, i1, i2, ctypes.byref(v)))
+    return v.value
+
+
+def selftest_special_host(which, x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty_like(x)
+    check(lib().rc_selftest_special_host(which, x.ctypes.data_as(ctypes.c_void_p),
+                                         y.ctypes.data_as(ctypes.c_void_p), x.size))
+    return y
+
+
+def selftest_step_host(spec, resid, coeffs, cells, dt, opts=None):
+    """Run the per-cell step on the host CPU (same source as the GPU kernel) on
+    tables in storage form (see Tables.from_storage).  Test use only."""
+    opts = opts or default_opts()
+    resid = np.ascontiguousarray(resid, dtype=np.float32).ravel()
+    coeffs = np.ascontiguousarray(coeffs, dtype=np.float64).ravel()
+    arrs = [np.ascontiguousarray(cells[k], dtype=np.float64) for k in ("n_e", "T_e", "T_i", "B", "H")]
+    n = arrs[0].size
+    outs = {k: np.empty(n) for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")}
+    outs["status"] = np.empty(n, dtype=np.uint8)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    check(lib().rc_selftest_step_host(ctypes.byref(spec), P(resid), P(coeffs), *[P(a) for a in arrs], n,
+                                      float(dt), ctypes.byref(opts),
+                                      P(outs["T_e_new"]), P(outs["T_i_new"]), P(outs["Q_rad"]),
+                                      P(outs["Q_cc"]), P(outs["status"])))
+    return outs

@@ -1,0 +1,120 @@
+"""The C-ABI library: it loads, exports every declared symbol, and rejects bad
+arguments on the host before anything is launched.  CPU only: no call here
+launches a kernel."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+R = pytest.importorskip("paper_2505_08855_amd.radcool")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(R.LIB_PATH):
+        pytest.fail("libradcool.so is not built (python -m paper_2505_08855_amd.build)")
+    return R.lib()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "radcool.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(rc_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(R.EXPORTED)
+
+
+def test_constants_match_oracle(L):
+    from oracle import constants as K
+    lib_c = R.constants()
+    want = [K.C_LIGHT, K.K_B, K.H_PLANCK, K.M_E, K.M_P, K.E_CHARGE, K.SIGMA_T, K.SIGMA_SB]
+    assert lib_c == want
+
+
+def test_default_spec_and_opts(L):
+    s = R.default_spec(64)
+    assert list(s.cool.n) == [64, 64, 64] and list(s.coul.n) == [64, 64, 64]
+    assert list(s.cool.lo) == [15.0, 5.95, -0.5] and list(s.cool.hi) == [29.0, 12.05, 10.5]
+    assert list(s.coul.lo) == [9.5, 5.95, 5.95] and list(s.coul.hi) == [20.5, 12.05, 14.05]
+    assert s.ln_lambda == 20.0
+    # the oracle's default axes are the same numbers
+    from oracle import tables as T
+    o = T.TableSpec.default(64)
+    for a in range(3):
+        assert (o.cool[a].lo, o.cool[a].hi) == (s.cool.lo[a], s.cool.hi[a])
+        assert (o.coul[a].lo, o.coul[a].hi) == (s.coul.lo[a], s.coul.hi[a])
+    op = R.default_opts()
+    assert (op.scheme, op.variant, op.max_iter, op.block, op.T_floor, op.tol) == (0, 0, 60, 0, 1e6, 1e-12)
+
+
+def test_argument_errors_without_launch(L):
+    assert L.rc_default_spec(None, 64) == -1
+    s = R.TableSpec()
+    assert L.rc_default_spec(ctypes.byref(s), 1) == -1
+    assert L.rc_default_opts(None) == -1
+    # invalid spec is rejected before any device work
+    bad = R.default_spec(64)
+    bad.cool.hi[0] = bad.cool.lo[0]
+    h = ctypes.c_void_p()
+    assert L.rc_build_tables(ctypes.byref(bad), None, ctypes.byref(h)) == -1
+    assert not h.value
+    assert b"spec" in L.rc_last_error()
+    assert L.rc_build_tables(ctypes.byref(bad), None, None) == -1
+    # import with NULL data
+    good = R.default_spec(8)
+    assert L.rc_tables_import(ctypes.byref(good), None, None, None, ctypes.byref(h)) == -1
+    # step with a NULL / bogus handle
+    st = R.State()
+    o = R.Out()
+    op = R.default_opts()
+    assert L.rc_cool_step(None, ctypes.byref(st), 10, 1e-8, ctypes.byref(op), ctypes.byref(o), None) == -5
+    fake = (ctypes.c_uint32 * 64)()
+    assert L.rc_cool_step(ctypes.cast(fake, ctypes.c_void_p), ctypes.byref(st), 10, 1e-8, ctypes.byref(op),
+                          ctypes.byref(o), None) == -5
+    assert L.rc_tables_destroy(ctypes.cast(fake, ctypes.c_void_p)) == -5
+    assert L.rc_tables_destroy(None) == 0
+    assert L.rc_tables_export(None, None, None) == -5
+    assert L.rc_tables_save(None, b"/tmp/x") == -5
+    assert L.rc_tables_load(None, None, ctypes.byref(h)) == -1
+    assert L.rc_tables_load(b"/nonexistent/file.rct", None, ctypes.byref(h)) == -6
+
+
+def test_tables_load_rejects_corrupt_files(L, tmp_path):
+    h = ctypes.c_void_p()
+    p = tmp_path / "junk.rct"
+    p.write_bytes(b"RCTABLE1" + b"\0" * 64)
+    assert L.rc_tables_load(str(p).encode(), None, ctypes.byref(h)) == -6
+    p.write_bytes(b"NOTMAGIC" + b"\0" * 400)
+    assert L.rc_tables_load(str(p).encode(), None, ctypes.byref(h)) == -6
+
+
+def test_selftest_argument_checks(L):
+    s = R.default_spec(8)
+    v = ctypes.c_double()
+    assert L.rc_selftest_node_host(ctypes.byref(s), 4, 0, 0, 0, ctypes.byref(v)) == -1
+    assert L.rc_selftest_node_host(ctypes.byref(s), 0, 8, 0, 0, ctypes.byref(v)) == -1
+    assert L.rc_selftest_special_host(9, None, None, 1) == -1
+    op = R.default_opts(max_iter=0)
+    x = np.ones(1)
+    resid = np.zeros(4 * 512, dtype=np.float32)
+    co = np.zeros(16)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    for bad_dt in (0.0, -1.0, float("nan"), float("inf")):
+        assert L.rc_selftest_step_host(ctypes.byref(s), P(resid), P(co), *[P(x)] * 5, 1, bad_dt,
+                                       ctypes.byref(R.default_opts()), None, None, None, None, None) == -1
+    assert L.rc_selftest_step_host(ctypes.byref(s), P(resid), P(co), *[P(x)] * 5, 1, 1e-8,
+                                   ctypes.byref(op), None, None, None, None, None) == -1
+    for field, val in (("scheme", 7), ("variant", 9), ("T_floor", -1.0), ("tol", 0.0), ("block", 96)):
+        op = R.default_opts(**{field: val})
+        assert L.rc_selftest_step_host(ctypes.byref(s), P(resid), P(co), *[P(x)] * 5, 1, 1e-8,
+                                       ctypes.byref(op), None, None, None, None, None) == -1, field

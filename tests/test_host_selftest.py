@@ -1,0 +1,110 @@
+"""The library's device source executed on the host CPU (test-only entry points
+rc_selftest_*_host) against the oracle.  These catch logic errors in the
+per-cell code before GPU time is spent; the parity claims themselves are made
+by the GPU tests, which run the same source as gfx950 kernels."""
+import numpy as np
+import pytest
+from scipy import special
+
+from conftest import rel_err
+from oracle import physics as P
+from oracle import step as S
+from oracle import tables as T
+from paper_2505_08855_amd import workloads as W
+
+R = pytest.importorskip("paper_2505_08855_amd.radcool")
+DT = W.DT_DEFAULT
+
+
+@pytest.fixture(scope="module")
+def storage64(tables64):
+    co, re, st = T.quantize_tables(tables64)
+    resid = np.concatenate([re[k].ravel() for k in T.TABLE_NAMES])
+    coeffs = np.stack([co[k] for k in T.TABLE_NAMES])
+    return resid, coeffs, st
+
+
+def test_scaled_bessels():
+    z = np.array([0.0053, 0.05, 0.3, 1.0, 7.0, 59.3, 300.0, 6600.0, 1e5, 1.2e7])
+    for nu in (0, 1, 2):
+        assert np.max(rel_err(R.selftest_special_host(nu, z), special.kve(nu, z))) < 2e-15
+
+
+def test_tail_integral_and_root():
+    x = np.array([1e-9, 1e-6, 1e-2, 0.7, 5.0, 80.0, 3e3, 1e5, 1e6])
+    # relative error grows like z * eps in the exponential factor, z = 1.89 x^(1/3)
+    assert np.max(rel_err(R.selftest_special_host(3, x), P.tail_integral(x))) < 1e-13
+    lr = np.linspace(-92, 37, 40)
+    assert np.max(rel_err(R.selftest_special_host(4, lr), P.solve_xc(lr))) < 1e-13
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_node_values_match_oracle(n):
+    spec = R.default_spec(n)
+    ospec = T.TableSpec.default(n)
+    rng = np.random.default_rng(n)
+    idx = np.concatenate([rng.integers(0, n, size=(60, 3)),
+                          np.array([[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, 0], [n - 1, 0, n - 1]])])
+    uN, uT, uB = (ospec.cool[a].nodes()[idx[:, a]] for a in range(3))
+    N, Te, B = 10.0 ** uN, 10.0 ** uT, 10.0 ** uB
+    one = np.ones_like(N)
+    sy = P.synchrotron(N, Te, B, one)
+    want = {0: np.log2(P.q_brem(N, Te)), 1: np.log2(sy["q_syn"]),
+            2: np.log2(P.compton_eta(N, Te, one, sy["nu_c"]))}
+    un, ue, ui = (ospec.coul[a].nodes()[idx[:, a]] for a in range(3))
+    want[3] = np.log2(P.coulomb_coeff(10.0 ** un, 10.0 ** ue, 10.0 ** ui))
+    for k in range(4):
+        got = np.array([R.selftest_node_host(spec, k, *[int(v) for v in row]) for row in idx])
+        assert np.max(np.abs(got - want[k])) < 1e-12, k
+
+
+def test_step_energy_tier_on_host(spec64, storage64, cells0_small):
+    """Backward Euler on identical (oracle-built, FP32-stored) tables: 1e-9 on T'."""
+    resid, coeffs, stored = storage64
+    ts = S.TableSet(spec64, stored)
+    cells = [cells0_small[f] for f in W.FIELDS]
+    ref = S.step_be(ts, *cells, DT)
+    got = R.selftest_step_host(R.default_spec(64), resid, coeffs, cells0_small, DT)
+    assert np.max(rel_err(got["T_e_new"], ref["T_e_new"])) < 1e-9
+    assert np.max(rel_err(got["T_i_new"], ref["T_i_new"])) < 1e-9
+    assert np.array_equal(got["status"], ref["status"])
+    assert np.max(rel_err(got["Q_rad"], ref["q_rad"])) < 1e-12
+    assert np.max(rel_err(got["Q_cc"], ref["q_cc"])) < 1e-12
+
+
+def test_step_explicit16_on_host(spec64, storage64, cells0_small):
+    resid, coeffs, stored = storage64
+    ts = S.TableSet(spec64, stored)
+    cells = [cells0_small[f] for f in W.FIELDS]
+    ref = S.step_explicit16(ts, *cells, DT)
+    got = R.selftest_step_host(R.default_spec(64), resid, coeffs, cells0_small, DT,
+                               R.default_opts(scheme="explicit16"))
+    assert np.max(rel_err(got["T_e_new"], ref["T_e_new"])) < 1e-12
+    assert np.max(rel_err(got["T_i_new"], ref["T_i_new"])) < 1e-12
+
+
+def test_step_edge_cases_on_host(spec64, storage64):
+    resid, coeffs, stored = storage64
+    ts = S.TableSet(spec64, stored)
+    cases = {  # n_e, T_e, T_i, B, H
+        "floor": (1e20, 2e6, 2e6, 1e8, 1e4),
+        "heating": (1e16, 1e8, 1e11, 10.0, 1e6),
+        "equal_T": (1e14, 1e9, 1e9, 1e4, 1e8),
+        "T_e_above_T_i": (1e15, 1e10, 1e9, 1e4, 1e8),
+        "clamped_low_n": (1e3, 1e8, 1e9, 1e2, 1e8),
+        "clamped_high_T": (1e12, 3e12, 1e15, 1e6, 1e8),
+        "below_floor": (1e12, 5e5, 2e5, 1e3, 1e8),
+        "invalid_nan": (np.nan, 1e8, 1e9, 1e3, 1e8),
+        "invalid_neg": (1e12, -1e8, 1e9, 1e3, 1e8),
+        "invalid_zero": (1e12, 1e8, 1e9, 0.0, 1e8),
+    }
+    arr = np.array(list(cases.values()), dtype=np.float64).T
+    cells = dict(zip(W.FIELDS, arr))
+    for dt, floor in ((DT, 1e6), (1e3 * DT, 1.5e6)):
+        ref = S.step_be(ts, *arr, dt, T_floor=floor)
+        got = R.selftest_step_host(R.default_spec(64), resid, coeffs, cells, dt, R.default_opts(T_floor=floor))
+        assert np.array_equal(got["status"], ref["status"]), (got["status"], ref["status"])
+        ok = (ref["status"] & 1) == 0
+        assert np.all(np.isnan(got["T_e_new"][~ok]))
+        assert np.max(rel_err(got["T_e_new"][ok], ref["T_e_new"][ok])) < 1e-9
+        assert np.max(rel_err(got["T_i_new"][ok], ref["T_i_new"][ok])) < 1e-9
