@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--sample", type=int, default=16384, help="cells in the cpu_baseline sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-variants", action="store_true")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="first run a plain 512 MiB device copy (known HBM traffic) for counter calibration")
     return p.parse_args()
 
 
@@ -115,6 +117,13 @@ def main():
         print("no HIP device visible", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float64, device=dev)    # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cells, desc = cells_for(args.workload)
     table_n = args.table_n if args.workload == "iid256" else 64
     n = cells["n_e"].size

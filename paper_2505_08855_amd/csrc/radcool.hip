@@ -454,7 +454,7 @@ extern "C" rc_status rc_selftest_step_host(const rc_table_spec* spec, const floa
     if (opts->variant == RC_VARIANT_DIRECT) {
       direct_rates(P, n_e[i], T_e[i], T_i[i], B[i], H[i], &o);
     } else {
-      cool_cell(tab, P, n_e[i], T_e[i], T_i[i], B[i], H[i], &o);
+      cool_cell_any(tab, P, n_e[i], T_e[i], T_i[i], B[i], H[i], false, &o);
     }
     if (T_e_new) T_e_new[i] = o.T_e_new;
     if (T_i_new) T_i_new[i] = o.T_i_new;

@@ -99,142 +99,148 @@ template <class Tab>
 struct CellSolver {
   const Tab& tab;
   const StepParams& P;
-  double n_e, T_e, T_i, B, H;
-  double c, S, tau_sca, invH, invH2, dt;
-  // cooling: fixed (N, B) coordinates, cached T cell
-  Coord cN, cB;
+  // per-cell constants
+  double T_e, T_i, H, c, cS, tau_sca, invH, invH2;
+  // gather coordinates that stay fixed during the solve
+  int iN, iB, in_;
+  double tN, tB, tn;
+  // cooling cache inside T cell iT: log2 v_brem = Ab + Sb t, log2(v_synch v_eta) = Ase + Sse t
   int iT;
-  double A[3], Sl[3];    // y_k(t) = A_k + Sl_k t inside cell iT
-  // Coulomb: fixed n_e coordinate, cached (T_e, T_i) cell
-  Coord cn;
+  double Ab, Ase, Sb, Sse;
+  // Coulomb cache inside cell (ie, ii): log2 v_c = K0 + c2 te + c3 ti + bilinear(v00, v10, v01, v11)
   int ie, ii;
   double K0, v00, v10, v01, v11;
-  // work counters: outer evaluations, inner Newton iterations, table-cell gathers
-  int n_outer = 0, n_inner = 0, n_gather = 0;
+  unsigned char clamp;
 
-  RC_HD CellSolver(const Tab& t, const StepParams& p) : tab(t), P(p), iT(-1), ie(-1), ii(-1) {}
+  RC_HD CellSolver(const Tab& t, const StepParams& p) : tab(t), P(p) {}
 
-  RC_HD void setup(double ne, double te, double ti, double b, double h) {
-    n_e = ne; T_e = te; T_i = ti; B = b; H = h;
-    dt = P.dt;
+  // per-cell constants and fixed coordinates; returns s0 = ln T_e
+  RC_HD double setup(double n_e, double te, double ti, double b, double h) {
+    T_e = te;
+    T_i = ti;
+    H = h;
     c = kUperNKT * n_e * kKB;
-    S = T_e + T_i;
-    tau_sca = 2.0 * n_e * kSigmaT * H;
-    invH = 1.0 / H;
+    cS = c * (te + ti);
+    tau_sca = 2.0 * n_e * kSigmaT * h;
+    invH = 1.0 / h;
     invH2 = invH * invH;
     const double lne = log10(n_e);
-    cN = axis_coord(lne + log10(H), P.ax[0]);
-    cB = axis_coord(log10(B), P.ax[2]);
-    cn = axis_coord(lne, P.ax[3]);
-    iT = -1;
-    ie = -1;
-    ii = -1;
+    const Coord cN = axis_coord(lne + log10(h), P.ax[0]);
+    const Coord cB = axis_coord(log10(b), P.ax[2]);
+    const Coord cn = axis_coord(lne, P.ax[3]);
+    iN = cN.i; tN = cN.t;
+    iB = cB.i; tB = cB.t;
+    in_ = cn.i; tn = cn.t;
+    const double s0 = log(te);
+    const double lte = s0 * (1.0 / kLn10);
+    clamp = 0;
+    if (cN.clamped || cB.clamped || axis_coord(lte, P.ax[1]).clamped) clamp |= ST_CLAMP_COOL;
+    if (cn.clamped || axis_coord(lte, P.ax[4]).clamped || axis_coord(log10(ti), P.ax[5]).clamped)
+      clamp |= ST_CLAMP_COUL;
+    iT = ie = ii = -1;
+    return s0;
   }
 
   // gather the 8 cooling corners of T cell i and reduce them along (N, B)
   RC_HD void load_cool(int i) {
     iT = i;
-    ++n_gather;
-    const double wN[2] = {1.0 - cN.t, cN.t};
-    const double wB[2] = {1.0 - cB.t, cB.t};
-    double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+    const double wN[2] = {1.0 - tN, tN};
+    const double wB[2] = {1.0 - tB, tB};
+    double lb = 0.0, lse = 0.0, hb = 0.0, hse = 0.0;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         const double w = wN[a] * wB[b];
-        const float4 p = tab.cool_at(cN.i + a, i, cB.i + b);
-        const float4 q = tab.cool_at(cN.i + a, i + 1, cB.i + b);
-        lo[0] += w * (double)p.x; lo[1] += w * (double)p.y; lo[2] += w * (double)p.z;
-        hi[0] += w * (double)q.x; hi[1] += w * (double)q.y; hi[2] += w * (double)q.z;
+        const float4 p = tab.cool_at(iN + a, i, iB + b);
+        const float4 q = tab.cool_at(iN + a, i + 1, iB + b);
+        lb += w * (double)p.x;
+        lse += w * ((double)p.y + (double)p.z);
+        hb += w * (double)q.x;
+        hse += w * ((double)q.y + (double)q.z);
       }
     }
-    const double fN = cN.i + cN.t, fB = cB.i + cB.t;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double* co = P.coef[k];
-      A[k] = co[0] + co[1] * fN + co[2] * (double)i + co[3] * fB + lo[k];
-      Sl[k] = co[2] + hi[k] - lo[k];
-    }
+    const double fN = iN + tN, fB = iB + tB;
+    const double* cb = P.coef[0];
+    const double* cs = P.coef[1];
+    const double* ce = P.coef[2];
+    Ab = cb[0] + cb[1] * fN + cb[2] * (double)i + cb[3] * fB + lb;
+    Sb = cb[2] + hb - lb;
+    Ase = (cs[0] + ce[0]) + (cs[1] + ce[1]) * fN + (cs[2] + ce[2]) * (double)i + (cs[3] + ce[3]) * fB + lse;
+    Sse = (cs[2] + ce[2]) + hse - lse;
   }
 
   RC_HD void load_coul(int je, int ji) {
-    ++n_gather;
     ie = je;
     ii = ji;
-    const double w0 = 1.0 - cn.t, w1 = cn.t;
-    v00 = w0 * tab.coul_at(cn.i, je, ji) + w1 * tab.coul_at(cn.i + 1, je, ji);
-    v10 = w0 * tab.coul_at(cn.i, je + 1, ji) + w1 * tab.coul_at(cn.i + 1, je + 1, ji);
-    v01 = w0 * tab.coul_at(cn.i, je, ji + 1) + w1 * tab.coul_at(cn.i + 1, je, ji + 1);
-    v11 = w0 * tab.coul_at(cn.i, je + 1, ji + 1) + w1 * tab.coul_at(cn.i + 1, je + 1, ji + 1);
+    const double w0 = 1.0 - tn, w1 = tn;
+    v00 = w0 * tab.coul_at(in_, je, ji) + w1 * tab.coul_at(in_ + 1, je, ji);
+    v10 = w0 * tab.coul_at(in_, je + 1, ji) + w1 * tab.coul_at(in_ + 1, je + 1, ji);
+    v01 = w0 * tab.coul_at(in_, je, ji + 1) + w1 * tab.coul_at(in_ + 1, je, ji + 1);
+    v11 = w0 * tab.coul_at(in_, je + 1, ji + 1) + w1 * tab.coul_at(in_ + 1, je + 1, ji + 1);
     const double* co = P.coef[3];
-    K0 = co[0] + co[1] * (cn.i + cn.t) + co[2] * (double)je + co[3] * (double)ji;
+    K0 = co[0] + co[1] * (in_ + tn) + co[2] * (double)je + co[3] * (double)ji;
   }
 
-  // cooling-table log2 values at T = exp(lnx): brem, synch + eta (summed),
-  // plus d/dln x of each
-  RC_HD void cool_y(double lnx, double* yb, double* yse, double* db, double* dse, Coord* cT) {
-    *cT = axis_coord(lnx * (1.0 / kLn10), P.ax[1]);
-    if (cT->i != iT) load_cool(cT->i);
-    const double t = cT->t;
-    *yb = A[0] + Sl[0] * t;
-    *yse = A[1] + A[2] + (Sl[1] + Sl[2]) * t;
-    const double g = cT->dfdu * (1.0 / kLn10);
-    *db = Sl[0] * g;
-    *dse = (Sl[1] + Sl[2]) * g;
-  }
-
-  // bridged Q_rad at T = x (zero when cooling is off) and dQ_rad/dln x
-  RC_HD void q_rad(double x, double lnx, bool on, double* q, double* dq) {
+  // bridged Q_rad at T = x (lx = log10 x; zero when cooling is off) and dQ_rad/dln x
+  RC_HD void q_rad(double x, double lx, bool on, double* q, double* dq) {
     if (!on) { *q = 0.0; *dq = 0.0; return; }
-    double yb, yse, db, dse;
-    Coord cT;
-    cool_y(lnx, &yb, &yse, &db, &dse, &cT);
-    const double vb = exp2(yb) * invH2;
-    const double vs = exp2(yse) * invH;
+    const Coord cT = axis_coord(lx, P.ax[1]);
+    if (cT.i != iT) load_cool(cT.i);
+    const double t = cT.t;
+    const double g = cT.dfdu * (1.0 / kLn10);       // d t / d ln x
+    const double vb = exp2(Ab + Sb * t) * invH2;
+    const double vs = exp2(Ase + Sse * t) * invH;
     const double qthin = vb + vs;
-    const double dlq = kLn2 * (vb * db + vs * dse) / qthin;
+    const double dlq = kLn2 * g * (vb * Sb + vs * Sse) / qthin;
     const double x2 = x * x;
     const double ta = H * qthin / (4.0 * kSigmaSB * x2 * x2);
     const double D = 1.0 + kSqrt3 * ta + 1.5 * ta * (ta + tau_sca);
     *q = qthin / D;
-    const double dta = ta * (dlq - 4.0);
-    const double dD = (kSqrt3 + 1.5 * (2.0 * ta + tau_sca)) * dta;
+    const double dD = (kSqrt3 + 1.5 * (2.0 * ta + tau_sca)) * ta * (dlq - 4.0);
     *dq = *q * (dlq - dD / D);
   }
 
-  // Coulomb coefficient v_c(x, z) and its partial derivatives d ln v_c / d ln x, d ln v_c / d ln z
-  RC_HD double kcoul(double x, double z, double* dlx, double* dlz, Coord* ce, Coord* ci) {
-    *ce = axis_coord(log10(x), P.ax[4]);
-    *ci = axis_coord(log10(z), P.ax[5]);
-    if (ce->i != ie || ci->i != ii) load_coul(ce->i, ci->i);
-    const double te = ce->t, ti = ci->t;
+  // Coulomb coefficient v_c at (T_e coordinate ce, T_i = z) and the partial
+  // derivatives d ln v_c / d ln T_e, d ln v_c / d ln T_i
+  RC_HD double kcoul(const Coord& ce, double z, double* dlx, double* dlz) {
+    const Coord ci = axis_coord(log10(z), P.ax[5]);
+    if (ce.i != ie || ci.i != ii) load_coul(ce.i, ci.i);
+    const double te = ce.t, ti = ci.t;
     const double c2 = P.coef[3][2], c3 = P.coef[3][3];
     const double y = K0 + c2 * te + c3 * ti + (1.0 - te) * (1.0 - ti) * v00 + te * (1.0 - ti) * v10 +
                      (1.0 - te) * ti * v01 + te * ti * v11;
     const double dye = c2 + (1.0 - ti) * (v10 - v00) + ti * (v11 - v01);
     const double dyi = c3 + (1.0 - te) * (v01 - v00) + te * (v11 - v10);
-    *dlx = kLn2 * dye * ce->dfdu * (1.0 / kLn10);
-    *dlz = kLn2 * dyi * ci->dfdu * (1.0 / kLn10);
+    *dlx = kLn2 * dye * ce.dfdu * (1.0 / kLn10);
+    *dlz = kLn2 * dyi * ci.dfdu * (1.0 / kLn10);
     return exp2(y);
   }
 
-  // z(x) solving E2; returns z and dz/dx
-  RC_HD double solve_z(double x, double zg, double* dzdx, int* iters) {
+  // z(x) solving E2 = c (z - T_i) + dt (z - x) v_c(x, z) = 0 inside
+  // [min(x, T_i), max(x, T_i)], where E2 changes sign; returns z and dz/dx.
+  // *K_first receives v_c at the first trial z (the warm start).
+  RC_HD double solve_z(double x, const Coord& ce, double zg, double* dzdx, double* K_first) {
+    const double dt = P.dt;
     double lo = fmin(x, T_i), hi = fmax(x, T_i);
-    if (!(hi > lo)) { *dzdx = 1.0; return lo; }
     double z = fmin(fmax(zg, lo), hi);
-    double dlx, dlz, K;
-    Coord ce, ci;
+    double K = 0.0, dlx = 0.0, dlz = 0.0;
+    if (!(hi > lo)) {
+      // x == T_i: z = T_i solves E2; implicit derivative dz/dx = dt K / (c + dt K)
+      K = kcoul(ce, z, &dlx, &dlz);
+      if (K_first) *K_first = K;
+      *dzdx = dt * K / (c + dt * K);
+      return lo;
+    }
+    double dEz = c;
     for (int it = 0; it < 60; ++it) {
-      K = kcoul(x, z, &dlx, &dlz, &ce, &ci);
+      K = kcoul(ce, z, &dlx, &dlz);
+      if (it == 0 && K_first) *K_first = K;
       const double E = c * (z - T_i) + dt * (z - x) * K;
+      dEz = c + dt * K + dt * (z - x) * K * dlz / z;
       if (E == 0.0) break;                  // z is an exact root
       if (E < 0.0) lo = z; else hi = z;
-      const double dE = c + dt * K + dt * (z - x) * K * dlz / z;
-      const double dz = -E / dE;
-      ++*iters;
-      ++n_inner;
+      const double dz = -E / dEz;
       // converged: Newton converges quadratically, so after a step below
       // 1e-8 z the remaining error is ~1e-16 z.  Tested before the bracket
       // safeguard, which would reject a step below the bracket end's ulp.
@@ -244,162 +250,211 @@ struct CellSolver {
       z = zn;
       if (hi - lo <= 1e-15 * z) break;
     }
-    K = kcoul(x, z, &dlx, &dlz, &ce, &ci);
-    const double dEz = c + dt * K + dt * (z - x) * K * dlz / z;
     const double dEx = -dt * K + dt * (z - x) * K * dlx / x;
     *dzdx = -dEx / dEz;
     return z;
   }
 
-  // outer residual G(s) and dG/ds at x = exp(s); z is updated in place
-  RC_HD double outer(double s, bool on, double* z, double* dG, int* iters) {
-    ++n_outer;
-    const double x = exp(s);
+  // outer residual G = log1p([c (x - T_e) + c (z - T_i) + dt Q_rad(x)] / (c (T_e + T_i)))
+  // at x = exp(s), its slope dG/ds, and (optionally) Q_rad(x) and v_c at the warm start
+  RC_HD double outer(double s, double x, bool on, double* z, double* dG, double* q_out, double* K_first) {
+    const double dt = P.dt;
+    const double lx = s * (1.0 / kLn10);
     double q, dq, dzdx;
-    q_rad(x, s, on, &q, &dq);
-    *z = solve_z(x, *z, &dzdx, iters);
+    q_rad(x, lx, on, &q, &dq);
+    const Coord ce = axis_coord(lx, P.ax[4]);
+    *z = solve_z(x, ce, *z, &dzdx, K_first);
     const double numer = c * ((x - T_e) + (*z - T_i)) + dt * q;
-    const double P_ = c * S + numer;
-    *dG = (c * x * (1.0 + dzdx) + dt * dq) / P_;
-    return log1p(numer / (c * S));
+    *dG = (c * x * (1.0 + dzdx) + dt * dq) / (cS + numer);
+    if (q_out) *q_out = q;
+    return log1p(numer / cS);
   }
 
-  // rates at the input state
-  RC_HD void rates(CellOut* o) {
-    double yb, yse, db, dse;
-    Coord cT;
-    cool_y(log(T_e), &yb, &yse, &db, &dse, &cT);
-    const double t = cT.t;
-    const double yb_ = A[0] + Sl[0] * t, ys_ = A[1] + Sl[1] * t, ye_ = A[2] + Sl[2] * t;
-    o->q_brem = exp2(yb_) * invH2;
-    o->q_syn = exp2(ys_) * invH;
-    o->eta = exp2(ye_);
-    const double qthin = o->q_brem + o->eta * o->q_syn;
-    const double T2 = T_e * T_e;
-    const double ta = H * qthin / (4.0 * kSigmaSB * T2 * T2);
-    o->q_rad = (T_e < P.T_floor) ? 0.0 : qthin / (1.0 + kSqrt3 * ta + 1.5 * ta * (ta + tau_sca));
-    double dlx, dlz;
-    Coord ce, ci;
-    const double K = kcoul(T_e, T_i, &dlx, &dlz, &ce, &ci);
-    o->q_cc = (T_i - T_e) * K;
-    unsigned char st = 0;
-    if (cN.clamped || cT.clamped || cB.clamped) st |= ST_CLAMP_COOL;
-    if (cn.clamped || ce.clamped || ci.clamped) st |= ST_CLAMP_COUL;
-    o->status = st;
-  }
-
-  RC_HD void newton(CellOut* o) {
-    const double s0 = log(T_e);
-    const double sf = log(P.T_floor);
+  // Newton driver.  Every evaluation of the outer residual goes through one
+  // call site (a small state machine picks the next point), so the inlined
+  // rate code exists once in the kernel.
+  RC_HD void newton(double s0, CellOut* o) {
+    enum { FIRST, ITER, PROBE_ON, PROBE_OFF, FINAL };
+    const double T_floor = P.T_floor;
+    const double sf = log(T_floor);
     const double tol = P.tol;
     const double step_tol = sqrt(tol);
+    // current iterate and its residual; bracket in s with G(lo) < 0 < G(hi)
+    double s = s0, G = 0.0, dG = 1.0, z = T_i;
+    double lo = 0.0, hi = 0.0;
+    bool lo_known = false;
+    bool floor_pending = false;   // a descent may still have to stop on the floor
+    bool heating = false;
+    double z_floor = T_i;         // ion temperature solved at the floor (projection)
+    // next evaluation point
+    int kind = FIRST;
+    double se = s0, xe = T_e;
+    bool on = T_e >= T_floor;
     int iters = 0;
-    double z = T_i, dG;
-    bool on = T_e >= P.T_floor;
-    double G = outer(s0, on, &z, &dG, &iters);
-    double s = s0;
-    unsigned char st = 0;
-    if (G == 0.0) { o->T_e_new = T_e; o->T_i_new = z; return; }
-    double lo, hi;           // bracket in s with G(lo) < 0 < G(hi)
-    bool lo_known, hi_known;
-    bool floor_pending = false;
-    if (G > 0.0) {
-      hi = s0; hi_known = true;
-      lo = log(fmin(T_i, P.T_floor)); lo_known = false;
-      floor_pending = on && (P.T_floor <= T_i);   // the floor, not T_i, bounds the descent
-      if (!floor_pending) lo_known = true;       // G(T_i) < 0 when everything is below the floor
-    } else {
-      lo = s0; lo_known = true;
-      hi = log(T_i); hi_known = true;
-      if (T_e < P.T_floor && P.T_floor < T_i) {
-        // the floor lies inside the bracket: decide which side holds the root
-        double zf = z, dGf;
-        const double Gm = outer(sf, false, &zf, &dGf, &iters);
-        if (Gm >= 0.0) {
-          hi = sf;                              // root below the floor, cooling off
+    for (;;) {
+      double ze = z, dGe, q, Kf;
+      const double Ge = outer(se, xe, on, &ze, &dGe, &q, &Kf);
+      bool propose = false;
+      if (kind == FINAL) {
+        o->T_e_new = xe;
+        o->T_i_new = ze;
+        return;
+      } else if (kind == FIRST) {
+        o->q_rad = q;
+        o->q_cc = (T_i - T_e) * Kf;
+        s = s0; G = Ge; dG = dGe; z = ze;
+        if (G == 0.0) { o->T_e_new = T_e; o->T_i_new = z; return; }
+        if (G > 0.0) {
+          hi = s0;
+          lo = log(fmin(T_i, T_floor));
+          floor_pending = on;
+          lo_known = !on;          // below the floor G(T_i) < 0 is guaranteed
+          propose = true;
         } else {
-          zf = z;
-          const double Gp = outer(sf, true, &zf, &dGf, &iters);
-          if (Gp >= 0.0) {
-            o->T_e_new = P.T_floor; o->T_i_new = zf; o->status |= ST_FLOOR; return;
+          heating = true;
+          lo = s0; lo_known = true;
+          hi = log(T_i);           // G(T_i) >= 0
+          if (T_e < T_floor && T_floor < T_i) {
+            // the floor lies inside the bracket: probe it with cooling off first
+            kind = PROBE_OFF; se = sf; xe = T_floor; on = false;
+          } else {
+            propose = true;
           }
-          lo = sf; s = sf; G = Gp; dG = dGf; z = zf;
         }
+      } else if (kind == PROBE_ON) {
+        z_floor = ze;
+        if (Ge < 0.0) {            // root above the floor
+          lo = sf; lo_known = true;
+          s = sf; G = Ge; dG = dGe; z = ze;
+          propose = true;
+        } else if (!heating && T_i < T_floor) {
+          // the root can also lie under the floor, where cooling is off
+          kind = PROBE_OFF; se = sf; xe = T_floor; on = false;
+        } else {
+          o->T_e_new = T_floor; o->T_i_new = ze; o->status |= ST_FLOOR;
+          return;
+        }
+      } else if (kind == PROBE_OFF) {
+        if (heating) {
+          if (Ge >= 0.0) {         // root below the floor, cooling off
+            hi = sf;
+            propose = true;
+          } else {
+            kind = PROBE_ON; se = sf; xe = T_floor; on = true;
+          }
+        } else if (Ge > 0.0) {     // descent continues under the floor
+          hi = sf; lo = log(T_i); lo_known = true;
+          s = sf; G = Ge; dG = dGe; z = ze;
+          propose = true;
+        } else {
+          o->T_e_new = T_floor; o->T_i_new = z_floor; o->status |= ST_FLOOR;
+          return;
+        }
+      } else {  // ITER
+        s = se; G = Ge; dG = dGe; z = ze;
+        if (G > 0.0) hi = s;
+        else if (G < 0.0) { lo = s; lo_known = true; }
+        if (G == 0.0 || (lo_known && (hi - lo) <= tol)) { o->T_e_new = xe; o->T_i_new = z; return; }
+        if (++iters >= P.max_iter) {
+          o->status |= ST_MAXITER;
+          o->T_e_new = xe; o->T_i_new = z;
+          return;
+        }
+        propose = true;
+      }
+      if (propose) {
+        double sn = s - G / dG;
+        const bool newton_ok = (dG > 0.0) && (sn == sn);
+        if (newton_ok && fabs(sn - s) <= step_tol && !(floor_pending && sn < sf)) {
+          // converged: Newton converges quadratically, so once the step is
+          // below sqrt(tol) the error left after taking it is O(tol); only
+          // z(x) remains to be solved at the new point.  Tested before the
+          // bracket safeguard, which could reject a step below an end's ulp.
+          kind = FINAL; se = sn; xe = exp(sn); on = false;
+          continue;
+        }
+        if (floor_pending && (!newton_ok || sn < sf)) {
+          // the descent would cross the floor (decided on the raw Newton step:
+          // the safeguard below only halves towards it): probe G just above it
+          floor_pending = false;
+          kind = PROBE_ON; se = sf; xe = T_floor; on = true;
+          continue;
+        }
+        if (!newton_ok || sn >= hi || (lo_known ? sn <= lo : sn < lo)) {
+          sn = lo_known ? 0.5 * (lo + hi) : 0.5 * (lo + s);
+        }
+        kind = ITER; se = sn; xe = exp(sn); on = xe >= T_floor;
       }
     }
-    bool done = false;
-    for (int it = 0; it < P.max_iter; ++it) {
-      double sn = s - G / dG;
-      const bool newton_ok = (dG > 0.0) && (sn == sn);
-      if (newton_ok && fabs(sn - s) <= step_tol && !(floor_pending && sn < sf)) {
-        // converged: Newton converges quadratically, so once the step is below
-        // sqrt(tol) the error left after taking it is O(tol).  Tested before
-        // the bracket safeguard, which could reject a step below an end's ulp.
-        s = sn;
-        double dzdx;
-        z = solve_z(exp(s), z, &dzdx, &iters);
-        done = true;
-        break;
-      }
-      if (floor_pending && newton_ok && sn < sf) {
-        // the step would cross the floor: probe G just above it
-        floor_pending = false;
-        double zf = z, dGf;
-        const double Gf = outer(sf, true, &zf, &dGf, &iters);
-        if (Gf >= 0.0) {
-          o->T_e_new = P.T_floor; o->T_i_new = zf; o->status |= ST_FLOOR; return;
-        }
-        lo = sf; lo_known = true;
-        s = sf; G = Gf; dG = dGf; z = zf;
-        continue;
-      }
-      if (!newton_ok || sn >= hi || sn <= lo || (!lo_known && sn < lo)) {
-        sn = lo_known ? 0.5 * (lo + hi) : 0.5 * (lo + s);
-      }
-      s = sn;
-      on = exp(s) >= P.T_floor;
-      G = outer(s, on, &z, &dG, &iters);
-      if (G > 0.0) { hi = s; hi_known = true; }
-      else if (G < 0.0) { lo = s; lo_known = true; }
-      else { done = true; break; }
-      if (lo_known && hi_known && (hi - lo) <= tol) {
-        done = true;
-        break;
-      }
-    }
-    if (!done) st |= ST_MAXITER;
-    o->T_e_new = exp(s);
-    o->T_i_new = z;
-    o->status |= st;
   }
 
-  RC_HD void explicit16(CellOut* o) {
+  RC_HD void explicit16(double s0, CellOut* o) {
+    const double dt = P.dt;
     const double h = dt / 16.0;
-    double te = T_e, ti = T_i;
+    double te = T_e, ti = T_i, lte = s0 * (1.0 / kLn10);
     for (int k = 0; k < 16; ++k) {
       double q, dq, dlx, dlz;
-      Coord ce, ci;
-      q_rad(te, log(te), te >= P.T_floor, &q, &dq);
-      const double K = kcoul(te, ti, &dlx, &dlz, &ce, &ci);
+      q_rad(te, lte, te >= P.T_floor, &q, &dq);
+      const double K = kcoul(axis_coord(lte, P.ax[4]), ti, &dlx, &dlz);
       const double qcc = (ti - te) * K;
+      if (k == 0) { o->q_rad = q; o->q_cc = qcc; }
       const double qr = fmin(q, 0.3 * c * te / h);
       const double lim = fmin(0.5 * c * fabs(ti - te), 0.3 * c * fmin(te, ti)) / h;
       const double qc = fmin(fmax(qcc, -lim), lim);
-      const double dte = h * (qc - qr) / c;
-      const double dti = -h * qc / c;
-      te += dte;
-      ti += dti;
+      te += h * (qc - qr) / c;
+      ti -= h * qc / c;
+      lte = log10(te);
     }
     o->T_e_new = te;
     o->T_i_new = ti;
+  }
+
+  RC_HD void rates(double s0, CellOut* o) {
+    const double lte = s0 * (1.0 / kLn10);
+    double q, dq, dlx, dlz;
+    q_rad(T_e, lte, T_e >= P.T_floor, &q, &dq);
+    o->q_rad = q;
+    o->q_cc = (T_i - T_e) * kcoul(axis_coord(lte, P.ax[4]), T_i, &dlx, &dlz);
+    o->T_e_new = T_e;
+    o->T_i_new = T_i;
+  }
+
+  // the three cooling quantities separately at the input state (diagnostic outputs)
+  RC_HD void diagnostics(double s0, CellOut* o) {
+    const Coord cT = axis_coord(s0 * (1.0 / kLn10), P.ax[1]);
+    const double wN[2] = {1.0 - tN, tN};
+    const double wB[2] = {1.0 - tB, tB};
+    const double wT[2] = {1.0 - cT.t, cT.t};
+    double y[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const double w = wN[a] * wT[m] * wB[b];
+          const float4 p = tab.cool_at(iN + a, cT.i + m, iB + b);
+          y[0] += w * (double)p.x;
+          y[1] += w * (double)p.y;
+          y[2] += w * (double)p.z;
+        }
+    const double fN = iN + tN, fT = cT.i + cT.t, fB = iB + tB;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double* co = P.coef[k];
+      y[k] += co[0] + co[1] * fN + co[2] * fT + co[3] * fB;
+    }
+    o->q_brem = exp2(y[0]) * invH2;
+    o->q_syn = exp2(y[1]) * invH;
+    o->eta = exp2(y[2]);
   }
 };
 
 RC_HD bool bad_input(double v) { return !(v > 0.0) || !isfinite(v); }
 
-template <class Tab>
+template <int SCHEME, class Tab>
 RC_HD void cool_cell(const Tab& tab, const StepParams& P, double n_e, double T_e, double T_i, double B,
-                     double H, CellOut* o) {
+                     double H, bool diag, CellOut* o) {
   if (bad_input(n_e) || bad_input(T_e) || bad_input(T_i) || bad_input(B) || bad_input(H)) {
     const double nan = __builtin_nan("");
     o->T_e_new = o->T_i_new = o->q_rad = o->q_cc = o->q_brem = o->q_syn = o->eta = nan;
@@ -407,16 +462,25 @@ RC_HD void cool_cell(const Tab& tab, const StepParams& P, double n_e, double T_e
     return;
   }
   CellSolver<Tab> cs(tab, P);
-  cs.setup(n_e, T_e, T_i, B, H);
-  cs.rates(o);
-  if (P.scheme == SCHEME_NEWTON) {
-    cs.newton(o);
-  } else if (P.scheme == SCHEME_EXPLICIT16) {
-    cs.explicit16(o);
+  const double s0 = cs.setup(n_e, T_e, T_i, B, H);
+  o->status = cs.clamp;
+  if (SCHEME == SCHEME_NEWTON) {
+    cs.newton(s0, o);
+  } else if (SCHEME == SCHEME_EXPLICIT16) {
+    cs.explicit16(s0, o);
   } else {
-    o->T_e_new = T_e;
-    o->T_i_new = T_i;
+    cs.rates(s0, o);
   }
+  if (diag) cs.diagnostics(s0, o);
+}
+
+// runtime scheme selection (host self-test path)
+template <class Tab>
+RC_HD void cool_cell_any(const Tab& tab, const StepParams& P, double n_e, double T_e, double T_i, double B,
+                         double H, bool diag, CellOut* o) {
+  if (P.scheme == SCHEME_NEWTON) cool_cell<SCHEME_NEWTON>(tab, P, n_e, T_e, T_i, B, H, diag, o);
+  else if (P.scheme == SCHEME_EXPLICIT16) cool_cell<SCHEME_EXPLICIT16>(tab, P, n_e, T_e, T_i, B, H, diag, o);
+  else cool_cell<SCHEME_RATES>(tab, P, n_e, T_e, T_i, B, H, diag, o);
 }
 
 // Table-free rates at the input state from the closed forms (DIRECT variant).

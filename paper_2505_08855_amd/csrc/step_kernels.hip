@@ -42,12 +42,13 @@ __device__ inline void store(const OutArgs& o, int64_t i, const CellOut& r) {
   if (o.status) o.status[i] = r.status;
 }
 
-template <class Tab>
+template <int SCHEME, class Tab>
 __global__ __launch_bounds__(256) void k_step(Tab tab, StepParams P, StateArgs s, OutArgs o, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   CellOut r;
-  cool_cell(tab, P, s.n_e[i], s.T_e[i], s.T_i[i], s.B[i], s.H[i], &r);
+  const bool diag = o.Q_brem || o.Q_syn || o.eta;
+  cool_cell<SCHEME>(tab, P, s.n_e[i], s.T_e[i], s.T_i[i], s.B[i], s.H[i], diag, &r);
   store(o, i, r);
 }
 
@@ -124,7 +125,12 @@ extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n,
     hipLaunchKernelGGL(k_direct, dim3((unsigned)grid), dim3(block), 0, hs, P, s, o, n);
   } else {
     GlobalTab tab{t->d_cool, t->d_coul, t->spec.cool.n[1], t->spec.cool.n[2], t->spec.coul.n[1], t->spec.coul.n[2]};
-    hipLaunchKernelGGL(k_step<GlobalTab>, dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, n);
+    if (opts->scheme == RC_SCHEME_NEWTON)
+      hipLaunchKernelGGL((k_step<SCHEME_NEWTON, GlobalTab>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, n);
+    else if (opts->scheme == RC_SCHEME_EXPLICIT16)
+      hipLaunchKernelGGL((k_step<SCHEME_EXPLICIT16, GlobalTab>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, n);
+    else
+      hipLaunchKernelGGL((k_step<SCHEME_RATES, GlobalTab>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, n);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "rc_cool_step launch");

@@ -108,3 +108,26 @@ def test_step_edge_cases_on_host(spec64, storage64):
         assert np.all(np.isnan(got["T_e_new"][~ok]))
         assert np.max(rel_err(got["T_e_new"][ok], ref["T_e_new"][ok])) < 1e-9
         assert np.max(rel_err(got["T_i_new"][ok], ref["T_i_new"][ok])) < 1e-9
+
+
+@pytest.mark.parametrize("floor", [3e6, 1e7, 5e7])
+def test_step_floor_branches_on_host(spec64, storage64, floor):
+    """Random cells around the floor: T_e and T_i on either side of it, strong
+    cooling (large dt), so that every branch of the floor handling runs."""
+    resid, coeffs, stored = storage64
+    ts = S.TableSet(spec64, stored)
+    rng = np.random.default_rng(int(floor))
+    n = 300
+    n_e = 10 ** rng.uniform(14, 20, n)
+    T_e = floor * 10 ** rng.uniform(-0.6, 0.8, n)
+    T_i = T_e * 10 ** rng.uniform(-1.0, 1.5, n)
+    B = np.sqrt(8 * np.pi * n_e * 1.380649e-16 * (T_e + T_i) / 10 ** rng.uniform(-1, 2, n))
+    H = 10 ** rng.uniform(5, 9, n)
+    dt = DT * 10 ** rng.uniform(0, 4)
+    cells = {"n_e": n_e, "T_e": T_e, "T_i": T_i, "B": B, "H": H}
+    ref = S.step_be(ts, n_e, T_e, T_i, B, H, dt, T_floor=floor)
+    got = R.selftest_step_host(R.default_spec(64), resid, coeffs, cells, dt, R.default_opts(T_floor=floor))
+    assert (ref["status"] & S.ST_FLOOR).sum() > 0
+    assert np.array_equal(got["status"], ref["status"])
+    assert np.max(rel_err(got["T_e_new"], ref["T_e_new"])) < 1e-9
+    assert np.max(rel_err(got["T_i_new"], ref["T_i_new"])) < 1e-9
