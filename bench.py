@@ -173,6 +173,26 @@ def main():
                 var[name] = {"ms": vms, "Gcell_per_s": n / (vms * 1e-3) / 1e9}
             except R.RadcoolError as e:
                 var[name] = {"error": str(e)}
+        # differentiation form: adjoint of the Newton step (cotangents of the
+        # radiated energy) with table-entry gradients
+        R.cool_step(tables, state, dt, opts, out=out)
+        c = 1.5 * state["n_e"] * 1.380649e-16
+        cot = {"T_e_new": -c, "T_i_new": -c}
+        _, nv = tables.info()
+        tg = torch.zeros(nv, dtype=torch.float64, device=dev)
+        fwd = {"T_e_new": out["T_e_new"], "T_i_new": out["T_i_new"], "status": out["status"]}
+        R.cool_step_backward(tables, state, dt, fwd, cot, opts, table_grad=tg)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            R.cool_step_backward(tables, state, dt, fwd, cot, opts, table_grad=tg)
+        e1.record()
+        torch.cuda.synchronize()
+        bms = e0.elapsed_time(e1) / 3
+        var["backward_newton"] = {"ms": bms, "Gcell_per_s": n / (bms * 1e-3) / 1e9}
+        del tg, c, cot
         res["variants"] = var
         # the timed configuration again, so that the outputs below are its own
         R.cool_step(tables, state, dt, opts, out=out)

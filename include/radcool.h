@@ -171,6 +171,50 @@ rc_status rc_tables_destroy(rc_tables t);
 rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n, double dt,
                        const rc_step_opts* opts, const rc_out* out, void* stream);
 
+/* Forward outputs the backward pass reads (device pointers, length n). */
+typedef struct {
+  const double* T_e_new;
+  const double* T_i_new;
+  const uint8_t* status;
+} rc_fwd;
+
+/* Upstream cotangents of the forward outputs (device pointers, length n);
+ * NULL = zero. */
+typedef struct {
+  const double* T_e_new;
+  const double* T_i_new;
+  const double* Q_rad;
+  const double* Q_cc;
+} rc_cotangent;
+
+/* Gradients written by the backward pass (device pointers).  The five
+ * per-cell arrays (length n) are overwritten; NULL = not written.  tables
+ * (n_values doubles, laid out as the residuals of rc_tables_import: gradient
+ * with respect to each table's log2 node values) is accumulated (+=) with
+ * device atomics, so its summation order, and the last bits of its values,
+ * vary from run to run; NULL = not computed. */
+typedef struct {
+  double* n_e;
+  double* T_e;
+  double* T_i;
+  double* B;
+  double* H;
+  double* tables;
+} rc_grad;
+
+/* Vector-Jacobian product of rc_cool_step (differentiation form).  For the
+ * Newton scheme the forward outputs define (T_e', T_i') implicitly through the
+ * backward-Euler equations of Sec. III.B.1; the adjoint solves the transposed
+ * 2x2 Jacobian per cell (implicit function theorem) at the converged solution
+ * (on a floor-projected cell T_e' is constant).  The input-state rates Q_rad,
+ * Q_cc add their direct derivatives.  RC_SCHEME_RATES is supported (T' = T);
+ * RC_SCHEME_EXPLICIT16 gives RC_EUNSUPPORTED.  fwd must hold the outputs of a
+ * forward call with the same tables, state, dt and options.  Asynchronous on
+ * stream. */
+rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, int64_t n, double dt,
+                                const rc_step_opts* opts, const rc_fwd* fwd, const rc_cotangent* cot,
+                                const rc_grad* grad, void* stream);
+
 /* The physical constants compiled into the library, in this order:
  * c, k_B, h, m_e, m_p, e, sigma_T, sigma_SB; returns how many were written
  * (at most n). */
@@ -198,6 +242,18 @@ rc_status rc_selftest_step_host(const rc_table_spec* spec, const float* resid, c
                                 const double* B, const double* H, int64_t n, double dt,
                                 const rc_step_opts* opts, double* T_e_new, double* T_i_new,
                                 double* Q_rad, double* Q_cc, uint8_t* status);
+
+/* Host-side self-test of the per-cell adjoint (same source as the GPU
+ * kernel) on tables in storage form (host memory).  Arrays of length n; cot_*
+ * may be NULL (zero); g_tables (n_values doubles) is accumulated.  For tests
+ * only. */
+rc_status rc_selftest_backward_host(const rc_table_spec* spec, const float* resid, const double* coeffs,
+                                    const double* n_e, const double* T_e, const double* T_i, const double* B,
+                                    const double* H, const double* T_e_new, const double* T_i_new,
+                                    const uint8_t* status, const double* cot_T_e_new, const double* cot_T_i_new,
+                                    const double* cot_Q_rad, const double* cot_Q_cc, int64_t n, double dt,
+                                    const rc_step_opts* opts, double* g_n_e, double* g_T_e, double* g_T_i,
+                                    double* g_B, double* g_H, double* g_tables);
 
 /* Message of the last error on this thread ("" if none). */
 const char* rc_last_error(void);

@@ -82,12 +82,16 @@ def qrad_parts(ts, n_e, x, B, H, T_floor):
     D = 1.0 + K.SQRT3 * ta + 1.5 * ta * (ta + ts_)
     D_ta = K.SQRT3 + 1.5 * (2.0 * ta + ts_)
     q = qt / D
+    # dQ_rad/dQ_thin including tau_abs's own dependence on Q_thin:
+    # (D - tau_abs dD/dtau_abs) / D^2 = (1 - 1.5 tau_abs^2) / D^2 exactly; the
+    # expanded form cancels catastrophically when scattering dominates
+    fac = (1.0 - 1.5 * ta ** 2) / D ** 2
     d = {}
     for p in ("n_e", "x", "B", "H"):
-        dta = ta * (dqt[p] / qt + (1.0 / H if p == "H" else 0.0) - (4.0 / x if p == "x" else 0.0))
+        # remaining explicit dependence of tau_abs (through H, x) and tau_sca (n_e, H)
+        dta = ta * ((1.0 / H if p == "H" else 0.0) - (4.0 / x if p == "x" else 0.0))
         dts = ts_ * ((1.0 / n_e if p == "n_e" else 0.0) + (1.0 / H if p == "H" else 0.0))
-        d[p] = dqt[p] / D - qt / D ** 2 * (D_ta * dta + 1.5 * ta * dts)
-    fac = (1.0 - D_ta * ta / D) / D          # dQ_rad / dQ_thin
+        d[p] = fac * dqt[p] - qt / D ** 2 * (D_ta * dta + 1.5 * ta * dts)
     d["tab"] = [("brem", ib, fac[:, None] * LN2 * vb[:, None] * wb),
                 ("synch", is_, fac[:, None] * LN2 * vse[:, None] * ws),
                 ("eta", ie, fac[:, None] * LN2 * vse[:, None] * we)]

@@ -1,0 +1,145 @@
+// Adjoint kernel and the rc_cool_step_backward entry point.
+//
+// One thread per cell: recompute the interpolant pieces at the forward
+// solution and at the input state, solve the transposed 2x2 system, write the
+// five input gradients (coalesced) and scatter the table-entry gradients with
+// FP64 atomics (native global_atomic_add_f64 on gfx950; the buffers are
+// coarse-grained device memory).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "radcool.h"
+#include "rc_grad.hpp"
+#include "rc_internal.hpp"
+
+namespace rc {
+
+struct BwdArgs {
+  const double *n_e, *T_e, *T_i, *B, *H;
+  const double *x, *z;
+  const uint8_t* status;
+  const double *g_x, *g_z, *g_qr, *g_qc;
+  double *o_n, *o_Te, *o_Ti, *o_B, *o_H, *o_tab;
+  int c1, c2, k1, k2;
+  long vc;
+  int newton;
+};
+
+template <class Tab>
+__global__ __launch_bounds__(256) void k_backward(Tab tab, StepParams P, BwdArgs a, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double* tabg = a.o_tab;
+  const long vc = a.vc;
+  auto add = [tabg, vc](int k, long idx, double v) {
+    if (tabg) atomicAdd(tabg + (k < 3 ? k * vc : 3 * vc) + idx, v);
+  };
+  CellGrad g;
+  const double x = a.newton ? a.x[i] : a.T_e[i];
+  const double z = a.newton ? a.z[i] : a.T_i[i];
+  const uint8_t st = a.status ? a.status[i] : (uint8_t)0;
+  cell_vjp(tab, P, a.c1, a.c2, a.k1, a.k2, a.n_e[i], a.T_e[i], a.T_i[i], a.B[i], a.H[i], x, z, st,
+           a.g_x ? a.g_x[i] : 0.0, a.g_z ? a.g_z[i] : 0.0, a.g_qr ? a.g_qr[i] : 0.0, a.g_qc ? a.g_qc[i] : 0.0,
+           a.newton != 0, &g, add);
+  if (a.o_n) a.o_n[i] = g.n_e;
+  if (a.o_Te) a.o_Te[i] = g.T_e;
+  if (a.o_Ti) a.o_Ti[i] = g.T_i;
+  if (a.o_B) a.o_B[i] = g.B;
+  if (a.o_H) a.o_H[i] = g.H;
+}
+
+}  // namespace rc
+
+using namespace rc;
+
+extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, int64_t n, double dt,
+                                           const rc_step_opts* opts, const rc_fwd* fwd, const rc_cotangent* cot,
+                                           const rc_grad* grad, void* stream) {
+  if (!handle_ok(t)) return set_error(RC_ESTATE, "rc_cool_step_backward: invalid table handle");
+  if (!state || !grad) return set_error(RC_EINVAL, "rc_cool_step_backward: state or grad is NULL");
+  if (n < 0) return set_error(RC_EINVAL, "rc_cool_step_backward: n < 0");
+  StepParams P;
+  rc_status st = make_params(t, dt, opts, &P);
+  if (st != RC_OK) return st;
+  if (opts->scheme == RC_SCHEME_EXPLICIT16)
+    return set_error(RC_EUNSUPPORTED, "rc_cool_step_backward: the explicit scheme has no adjoint");
+  if (opts->variant == RC_VARIANT_DIRECT)
+    return set_error(RC_EUNSUPPORTED, "rc_cool_step_backward: the DIRECT variant has no table adjoint");
+  const bool newton = opts->scheme == RC_SCHEME_NEWTON;
+  if (n > 0 && (!state->n_e || !state->T_e || !state->T_i || !state->B || !state->H))
+    return set_error(RC_EINVAL, "rc_cool_step_backward: a state pointer is NULL");
+  if (n > 0 && newton && (!fwd || !fwd->T_e_new || !fwd->T_i_new || !fwd->status))
+    return set_error(RC_EINVAL, "rc_cool_step_backward: the Newton scheme needs the forward T_e_new, T_i_new, status");
+  if (n == 0) return RC_OK;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != t->device)
+    return set_error(RC_ESTATE, "rc_cool_step_backward: tables live on another device than the current one");
+  BwdArgs a;
+  a.n_e = state->n_e; a.T_e = state->T_e; a.T_i = state->T_i; a.B = state->B; a.H = state->H;
+  a.x = fwd ? fwd->T_e_new : nullptr;
+  a.z = fwd ? fwd->T_i_new : nullptr;
+  a.status = fwd ? fwd->status : nullptr;
+  a.g_x = cot ? cot->T_e_new : nullptr;
+  a.g_z = cot ? cot->T_i_new : nullptr;
+  a.g_qr = cot ? cot->Q_rad : nullptr;
+  a.g_qc = cot ? cot->Q_cc : nullptr;
+  a.o_n = grad->n_e; a.o_Te = grad->T_e; a.o_Ti = grad->T_i; a.o_B = grad->B; a.o_H = grad->H;
+  a.o_tab = grad->tables;
+  a.c1 = t->spec.cool.n[1]; a.c2 = t->spec.cool.n[2];
+  a.k1 = t->spec.coul.n[1]; a.k2 = t->spec.coul.n[2];
+  a.vc = (long)volume(t->spec.cool);
+  a.newton = newton ? 1 : 0;
+  const int block = opts->block ? opts->block : 256;
+  const int64_t grid = (n + block - 1) / block;
+  if (grid > 0x7fffffffLL) return set_error(RC_EINVAL, "rc_cool_step_backward: n too large for one launch");
+  GlobalTab tab{t->d_cool, t->d_coul, t->spec.cool.n[1], t->spec.cool.n[2], t->spec.coul.n[1], t->spec.coul.n[2]};
+  hipLaunchKernelGGL(k_backward<GlobalTab>, dim3((unsigned)grid), dim3(block), 0, (hipStream_t)stream, tab, P, a, n);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "rc_cool_step_backward launch");
+  return RC_OK;
+}
+
+extern "C" rc_status rc_selftest_backward_host(const rc_table_spec* spec, const float* resid, const double* coeffs,
+                                               const double* n_e, const double* T_e, const double* T_i,
+                                               const double* B, const double* H, const double* T_e_new,
+                                               const double* T_i_new, const uint8_t* status,
+                                               const double* cot_T_e_new, const double* cot_T_i_new,
+                                               const double* cot_Q_rad, const double* cot_Q_cc, int64_t n,
+                                               double dt, const rc_step_opts* opts, double* g_n_e, double* g_T_e,
+                                               double* g_T_i, double* g_B, double* g_H, double* g_tables) {
+  if (!spec_ok(spec) || !resid || !coeffs) return set_error(RC_EINVAL, "rc_selftest_backward_host: bad table arguments");
+  if (!n_e || !T_e || !T_i || !B || !H || !opts || n < 0)
+    return set_error(RC_EINVAL, "rc_selftest_backward_host: bad argument");
+  rc_tables_s host;
+  host.spec = *spec;
+  for (int k = 0; k < 4; ++k)
+    for (int j = 0; j < 4; ++j) host.coef[k][j] = coeffs[4 * k + j];
+  StepParams P;
+  rc_status st = make_params(&host, dt, opts, &P);
+  if (st != RC_OK) return st;
+  const bool newton = opts->scheme == RC_SCHEME_NEWTON;
+  if (opts->scheme == RC_SCHEME_EXPLICIT16) return set_error(RC_EUNSUPPORTED, "explicit scheme has no adjoint");
+  if (newton && (!T_e_new || !T_i_new || !status)) return set_error(RC_EINVAL, "forward outputs required");
+  const long vc = (long)volume(spec->cool);
+  std::vector<float4> cool((size_t)vc);
+  for (long i = 0; i < vc; ++i) cool[i] = make_float4(resid[i], resid[vc + i], resid[2 * vc + i], 0.0f);
+  GlobalTab tab{cool.data(), resid + 3 * vc, spec->cool.n[1], spec->cool.n[2], spec->coul.n[1], spec->coul.n[2]};
+  auto add = [g_tables, vc](int k, long idx, double v) {
+    if (g_tables) g_tables[(k < 3 ? k * vc : 3 * vc) + idx] += v;
+  };
+  for (int64_t i = 0; i < n; ++i) {
+    CellGrad g;
+    cell_vjp(tab, P, spec->cool.n[1], spec->cool.n[2], spec->coul.n[1], spec->coul.n[2], n_e[i], T_e[i], T_i[i],
+             B[i], H[i], newton ? T_e_new[i] : T_e[i], newton ? T_i_new[i] : T_i[i], status ? status[i] : 0,
+             cot_T_e_new ? cot_T_e_new[i] : 0.0, cot_T_i_new ? cot_T_i_new[i] : 0.0,
+             cot_Q_rad ? cot_Q_rad[i] : 0.0, cot_Q_cc ? cot_Q_cc[i] : 0.0, newton, &g, add);
+    if (g_n_e) g_n_e[i] = g.n_e;
+    if (g_T_e) g_T_e[i] = g.T_e;
+    if (g_T_i) g_T_i[i] = g.T_i;
+    if (g_B) g_B[i] = g.B;
+    if (g_H) g_H[i] = g.H;
+  }
+  return RC_OK;
+}

@@ -1,0 +1,240 @@
+// Per-cell adjoint of the cooling step (host + device source).
+//
+// The backward-Euler update defines (x, z) = (T_e', T_i') by
+//   E1 = c (x - T_e) + dt Q_rad(x) - dt (z - x) v_c(x, z) = 0,
+//   E2 = c (z - T_i) + dt (z - x) v_c(x, z)               = 0,
+// so for output cotangents (g_x, g_z) the vector-Jacobian product follows from
+// the implicit function theorem: solve J^T lam = (g_x, g_z) with
+// J = d(E1, E2)/d(x, z) (the same 2x2 Jacobian the Newton solve uses) and
+// gbar_p = -lam . d(E1, E2)/dp.  A floor-projected cell has x fixed, so only E2
+// ties z to the inputs.  The input-state rates Q_rad(T_e), Q_cc(T_e, T_i) add
+// their direct derivatives.  Table entries are the log2 node values; a value
+// 2^y depends on a corner through ln 2 * 2^y * (corner weight).  Derivatives
+// are those of the interpolant inside the query's cell (zero along a clamped
+// axis), as in the forward solve.
+#pragma once
+
+#include "rc_step.hpp"
+
+namespace rc {
+
+// trilinear point of the interleaved cooling tables: log2 of v_brem and of
+// v_synch * v_eta with their gradients in the log10 coordinates, and corners
+struct CoolPoint {
+  double yb, yse;
+  double dyb[3], dyse[3];
+  long idx[8];
+  double w[8];
+};
+
+struct CoulPoint {
+  double y;
+  double dy[3];
+  long idx[8];
+  double w[8];
+};
+
+template <class Tab>
+RC_HD CoolPoint cool_point(const Tab& tab, const StepParams& P, double u0, double u1, double u2, int n1, int n2) {
+  const Coord c0 = axis_coord(u0, P.ax[0]), c1 = axis_coord(u1, P.ax[1]), c2 = axis_coord(u2, P.ax[2]);
+  CoolPoint r;
+  double yb = 0.0, ys = 0.0, ye = 0.0;
+  double gb[3] = {0.0, 0.0, 0.0}, gse[3] = {0.0, 0.0, 0.0};
+  int k = 0;
+  for (int a = 0; a < 2; ++a) {
+    const double wa = a ? c0.t : 1.0 - c0.t, da = a ? 1.0 : -1.0;
+    for (int b = 0; b < 2; ++b) {
+      const double wb = b ? c1.t : 1.0 - c1.t, db = b ? 1.0 : -1.0;
+      for (int m = 0; m < 2; ++m, ++k) {
+        const double wm = m ? c2.t : 1.0 - c2.t, dm = m ? 1.0 : -1.0;
+        const float4 p = tab.cool_at(c0.i + a, c1.i + b, c2.i + m);
+        const double w = wa * wb * wm;
+        const double vb = p.x, vse = (double)p.y + (double)p.z;
+        yb += w * vb;
+        ys += w * (double)p.y;
+        ye += w * (double)p.z;
+        const double g0 = da * wb * wm, g1 = wa * db * wm, g2 = wa * wb * dm;
+        gb[0] += g0 * vb; gb[1] += g1 * vb; gb[2] += g2 * vb;
+        gse[0] += g0 * vse; gse[1] += g1 * vse; gse[2] += g2 * vse;
+        r.idx[k] = ((long)(c0.i + a) * n1 + (c1.i + b)) * n2 + (c2.i + m);
+        r.w[k] = w;
+      }
+    }
+  }
+  const double f0 = c0.i + c0.t, f1 = c1.i + c1.t, f2 = c2.i + c2.t;
+  const double* cb = P.coef[0];
+  const double* cs = P.coef[1];
+  const double* ce = P.coef[2];
+  r.yb = cb[0] + cb[1] * f0 + cb[2] * f1 + cb[3] * f2 + yb;
+  r.yse = (cs[0] + ce[0]) + (cs[1] + ce[1]) * f0 + (cs[2] + ce[2]) * f1 + (cs[3] + ce[3]) * f2 + ys + ye;
+  const double dfdu[3] = {c0.dfdu, c1.dfdu, c2.dfdu};
+  for (int q = 0; q < 3; ++q) {
+    r.dyb[q] = (cb[q + 1] + gb[q]) * dfdu[q];
+    r.dyse[q] = (cs[q + 1] + ce[q + 1] + gse[q]) * dfdu[q];
+  }
+  return r;
+}
+
+template <class Tab>
+RC_HD CoulPoint coul_point(const Tab& tab, const StepParams& P, double u0, double u1, double u2, int n1, int n2) {
+  const Coord c0 = axis_coord(u0, P.ax[3]), c1 = axis_coord(u1, P.ax[4]), c2 = axis_coord(u2, P.ax[5]);
+  CoulPoint r;
+  double y = 0.0, g[3] = {0.0, 0.0, 0.0};
+  int k = 0;
+  for (int a = 0; a < 2; ++a) {
+    const double wa = a ? c0.t : 1.0 - c0.t, da = a ? 1.0 : -1.0;
+    for (int b = 0; b < 2; ++b) {
+      const double wb = b ? c1.t : 1.0 - c1.t, db = b ? 1.0 : -1.0;
+      for (int m = 0; m < 2; ++m, ++k) {
+        const double wm = m ? c2.t : 1.0 - c2.t, dm = m ? 1.0 : -1.0;
+        const double v = tab.coul_at(c0.i + a, c1.i + b, c2.i + m);
+        const double w = wa * wb * wm;
+        y += w * v;
+        g[0] += da * wb * wm * v; g[1] += wa * db * wm * v; g[2] += wa * wb * dm * v;
+        r.idx[k] = ((long)(c0.i + a) * n1 + (c1.i + b)) * n2 + (c2.i + m);
+        r.w[k] = w;
+      }
+    }
+  }
+  const double* co = P.coef[3];
+  r.y = co[0] + co[1] * (c0.i + c0.t) + co[2] * (c1.i + c1.t) + co[3] * (c2.i + c2.t) + y;
+  const double dfdu[3] = {c0.dfdu, c1.dfdu, c2.dfdu};
+  for (int q = 0; q < 3; ++q) r.dy[q] = (co[q + 1] + g[q]) * dfdu[q];
+  return r;
+}
+
+// Q_rad at T_e' = x and its partial derivatives (n_e, x, B, H), plus dQ_rad/dy
+// per unit corner weight for the brem table (sb) and for the synch and eta
+// tables (sse, the same for both since they enter as a product).
+struct QradPartials {
+  double q, dn, dx, dB, dH, sb, sse;
+};
+
+RC_HD QradPartials qrad_partials(const CoolPoint& cp, double n_e, double x, double B, double H, bool on) {
+  QradPartials r = {0, 0, 0, 0, 0, 0, 0};
+  if (!on) return r;
+  const double vb = exp2(cp.yb) / (H * H);
+  const double vse = exp2(cp.yse) / H;
+  const double qt = vb + vse;
+  double du[3];
+  for (int a = 0; a < 3; ++a) du[a] = kLn2 * (vb * cp.dyb[a] + vse * cp.dyse[a]);
+  const double dqt_n = du[0] / (n_e * kLn10);
+  const double dqt_x = du[1] / (x * kLn10);
+  const double dqt_B = du[2] / (B * kLn10);
+  const double dqt_H = du[0] / (H * kLn10) - 2.0 * vb / H - vse / H;
+  const double ts = 2.0 * n_e * kSigmaT * H;
+  const double x2 = x * x;
+  const double ta = H * qt / (4.0 * kSigmaSB * x2 * x2);
+  const double D = 1.0 + kSqrt3 * ta + 1.5 * ta * (ta + ts);
+  const double Dta = kSqrt3 + 1.5 * (2.0 * ta + ts);
+  const double q = qt / D;
+  const double iD = 1.0 / D, qD2 = qt * iD * iD;
+  // dQ_rad/dQ_thin with tau_abs's own dependence on Q_thin:
+  // (D - ta dD/dta) / D^2 = (1 - 1.5 ta^2) / D^2 exactly (the expanded form
+  // cancels when scattering dominates); the rest is the explicit dependence of
+  // ta on H and x and of ts on n_e and H
+  const double fac = (1.0 - 1.5 * ta * ta) * iD * iD;
+  r.q = q;
+  r.dn = fac * dqt_n - qD2 * 1.5 * ta * ts / n_e;
+  r.dx = fac * dqt_x + qD2 * Dta * 4.0 * ta / x;
+  r.dB = fac * dqt_B;
+  r.dH = fac * dqt_H - qD2 * (Dta * ta + 1.5 * ta * ts) / H;
+  r.sb = fac * kLn2 * vb;
+  r.sse = fac * kLn2 * vse;
+  return r;
+}
+
+struct CellGrad {
+  double n_e, T_e, T_i, B, H;
+};
+
+// Adjoint of one cell.  (x, z, status) are the forward outputs; add(k, idx, v)
+// accumulates v into the gradient of table k (0 brem, 1 synch, 2 eta, 3 coul)
+// at flat node index idx.
+template <class Tab, class Add>
+RC_HD void cell_vjp(const Tab& tab, const StepParams& P, int c1, int c2, int k1, int k2, double n_e, double T_e,
+                    double T_i, double B, double H, double x, double z, unsigned char status, double g_x,
+                    double g_z, double g_qr, double g_qc, bool newton, CellGrad* out, Add add) {
+  out->n_e = out->T_e = out->T_i = out->B = out->H = 0.0;
+  if (status & ST_INVALID) return;
+  const double dt = P.dt;
+  const double c = kUperNKT * n_e * kKB;
+  const double c_n = kUperNKT * kKB;
+  const double lne = log10(n_e), lH = log10(H), lB = log10(B);
+  double gn = 0.0, gTe = 0.0, gTi = 0.0, gB = 0.0, gH = 0.0;
+  if (newton) {
+    const bool floor = (status & ST_FLOOR) != 0;
+    const double lx = log10(x), lz = log10(z);
+    const CoolPoint cp = cool_point(tab, P, lne + lH, lx, lB, c1, c2);
+    const CoulPoint kp = coul_point(tab, P, lne, lx, lz, k1, k2);
+    const QradPartials qp = qrad_partials(cp, n_e, x, B, H, x >= P.T_floor);
+    const double kc = exp2(kp.y);
+    const double kn = kLn2 * kc * kp.dy[0] / (n_e * kLn10);
+    const double kx = kLn2 * kc * kp.dy[1] / (x * kLn10);
+    const double kz = kLn2 * kc * kp.dy[2] / (z * kLn10);
+    const double zx = z - x;
+    const double j11 = c + dt * qp.dx + dt * kc - dt * zx * kx;
+    const double j12 = -dt * kc - dt * zx * kz;
+    const double j21 = -dt * kc + dt * zx * kx;
+    const double j22 = c + dt * kc + dt * zx * kz;
+    double l1, l2;
+    if (floor) {
+      l1 = 0.0;
+      l2 = g_z / j22;
+    } else {
+      const double det = j11 * j22 - j12 * j21;
+      l1 = (j22 * g_x - j21 * g_z) / det;
+      l2 = (j11 * g_z - j12 * g_x) / det;
+    }
+    gn = -(l1 * (c_n * (x - T_e) + dt * qp.dn - dt * zx * kn) + l2 * (c_n * (z - T_i) + dt * zx * kn));
+    gTe = l1 * c;
+    gTi = l2 * c;
+    gB = -l1 * dt * qp.dB;
+    gH = -l1 * dt * qp.dH;
+    const double a_b = -l1 * dt * qp.sb, a_se = -l1 * dt * qp.sse;
+    const double a_c = (l1 - l2) * dt * zx * kLn2 * kc;
+    for (int k = 0; k < 8; ++k) {
+      if (a_b != 0.0) add(0, cp.idx[k], a_b * cp.w[k]);
+      if (a_se != 0.0) {
+        add(1, cp.idx[k], a_se * cp.w[k]);
+        add(2, cp.idx[k], a_se * cp.w[k]);
+      }
+      if (a_c != 0.0) add(3, kp.idx[k], a_c * kp.w[k]);
+    }
+  } else {
+    gTe = g_x;    // rates only: T' = T
+    gTi = g_z;
+  }
+  if (g_qr != 0.0 || g_qc != 0.0) {
+    const double lte = log10(T_e), lti = log10(T_i);
+    const CoolPoint cp = cool_point(tab, P, lne + lH, lte, lB, c1, c2);
+    const CoulPoint kp = coul_point(tab, P, lne, lte, lti, k1, k2);
+    const QradPartials qp = qrad_partials(cp, n_e, T_e, B, H, T_e >= P.T_floor);
+    const double kc = exp2(kp.y);
+    const double kn = kLn2 * kc * kp.dy[0] / (n_e * kLn10);
+    const double kx = kLn2 * kc * kp.dy[1] / (T_e * kLn10);
+    const double kz = kLn2 * kc * kp.dy[2] / (T_i * kLn10);
+    const double gap = T_i - T_e;
+    gn += g_qr * qp.dn + g_qc * gap * kn;
+    gTe += g_qr * qp.dx + g_qc * (-kc + gap * kx);
+    gTi += g_qc * (kc + gap * kz);
+    gB += g_qr * qp.dB;
+    gH += g_qr * qp.dH;
+    const double a_b = g_qr * qp.sb, a_se = g_qr * qp.sse, a_c = g_qc * gap * kLn2 * kc;
+    for (int k = 0; k < 8; ++k) {
+      if (a_b != 0.0) add(0, cp.idx[k], a_b * cp.w[k]);
+      if (a_se != 0.0) {
+        add(1, cp.idx[k], a_se * cp.w[k]);
+        add(2, cp.idx[k], a_se * cp.w[k]);
+      }
+      if (a_c != 0.0) add(3, kp.idx[k], a_c * kp.w[k]);
+    }
+  }
+  out->n_e = gn;
+  out->T_e = gTe;
+  out->T_i = gTi;
+  out->B = gB;
+  out->H = gH;
+}
+
+}  // namespace rc

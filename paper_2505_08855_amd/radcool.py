@@ -27,7 +27,8 @@ SCHEMES = {"newton": 0, "explicit16": 1, "rates": 2}
 EXPORTED = ("rc_default_spec", "rc_default_opts", "rc_build_tables", "rc_tables_import",
             "rc_tables_export", "rc_tables_info", "rc_tables_save", "rc_tables_load",
             "rc_tables_destroy", "rc_cool_step", "rc_constants", "rc_selftest_node_host",
-            "rc_selftest_special_host", "rc_selftest_step_host", "rc_last_error")
+            "rc_selftest_special_host", "rc_selftest_step_host", "rc_last_error",
+            "rc_cool_step_backward", "rc_selftest_backward_host")
 
 
 class RadcoolError(RuntimeError):
@@ -51,6 +52,18 @@ class State(ctypes.Structure):
 class Out(ctypes.Structure):
     _fields_ = [(f, ctypes.c_void_p) for f in ("T_e_new", "T_i_new", "Q_rad", "Q_cc", "status",
                                                "Q_brem", "Q_syn", "eta")]
+
+
+class Fwd(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in ("T_e_new", "T_i_new", "status")]
+
+
+class Cotangent(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")]
+
+
+class Grad(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in ("n_e", "T_e", "T_i", "B", "H", "tables")]
 
 
 class StepOpts(ctypes.Structure):
@@ -87,6 +100,9 @@ def lib():
             "rc_selftest_step_host": (i32, [P(TableSpec), vp, vp, vp, vp, vp, vp, vp, i64, dbl,
                                             P(StepOpts), vp, vp, vp, vp, vp]),
             "rc_last_error": (ctypes.c_char_p, []),
+            "rc_cool_step_backward": (i32, [vp, P(State), i64, dbl, P(StepOpts), P(Fwd), P(Cotangent), P(Grad), vp]),
+            "rc_selftest_backward_host": (i32, [P(TableSpec), vp, vp] + [vp] * 12 + [i64, dbl, P(StepOpts)]
+                                          + [vp] * 6),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -254,6 +270,29 @@ def cool_step(tables, state, dt, opts=None, out=None, diagnostics=False, stream=
     return out
 
 
+def cool_step_backward(tables, state, dt, fwd, cot, opts=None, table_grad=None, stream=None):
+    """Vector-Jacobian product of cool_step.  ``fwd``: dict with T_e_new, T_i_new,
+    status from the forward call; ``cot``: dict of cotangent tensors (any of
+    T_e_new, T_i_new, Q_rad, Q_cc; missing = 0).  Returns a dict of input
+    gradients (n_e, T_e, T_i, B, H); if ``table_grad`` (a float64 tensor of
+    n_values) is given, table-entry gradients are accumulated into it."""
+    import torch
+    n = _check_state(state)
+    opts = opts or default_opts()
+    dev = state["n_e"].device
+    g = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("n_e", "T_e", "T_i", "B", "H")}
+    st = State(*[state[k].data_ptr() for k in ("n_e", "T_e", "T_i", "B", "H")])
+    fw = Fwd(*[fwd[k].data_ptr() if fwd is not None and fwd.get(k) is not None else None
+               for k in ("T_e_new", "T_i_new", "status")])
+    ct = Cotangent(*[cot[k].contiguous().data_ptr() if cot.get(k) is not None else None
+                     for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")])
+    gr = Grad(*[g[k].data_ptr() for k in ("n_e", "T_e", "T_i", "B", "H")],
+              table_grad.data_ptr() if table_grad is not None else None)
+    check(lib().rc_cool_step_backward(tables.handle, ctypes.byref(st), n, float(dt), ctypes.byref(opts),
+                                      ctypes.byref(fw), ctypes.byref(ct), ctypes.byref(gr), _stream_ptr(stream)))
+    return g
+
+
 def constants():
     buf = (ctypes.c_double * 8)()
     m = lib().rc_constants(buf, 8)
@@ -293,3 +332,24 @@ def selftest_step_host(spec, resid, coeffs, cells, dt, opts=None):
                                       P(outs["T_e_new"]), P(outs["T_i_new"]), P(outs["Q_rad"]),
                                       P(outs["Q_cc"]), P(outs["status"])))
     return outs
+
+
+def selftest_backward_host(spec, resid, coeffs, cells, fwd, cot, dt, opts=None):
+    """Run the per-cell adjoint on the host CPU (same source as the GPU kernel).
+    Returns (input gradients dict, table gradient array).  Test use only."""
+    opts = opts or default_opts()
+    resid = np.ascontiguousarray(resid, dtype=np.float32).ravel()
+    coeffs = np.ascontiguousarray(coeffs, dtype=np.float64).ravel()
+    arrs = [np.ascontiguousarray(cells[k], dtype=np.float64) for k in ("n_e", "T_e", "T_i", "B", "H")]
+    n = arrs[0].size
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+    fw = [np.ascontiguousarray(fwd["T_e_new"], dtype=np.float64), np.ascontiguousarray(fwd["T_i_new"], dtype=np.float64),
+          np.ascontiguousarray(fwd["status"], dtype=np.uint8)]
+    ct = [None if cot.get(k) is None else np.ascontiguousarray(np.broadcast_to(cot[k], (n,)), dtype=np.float64)
+          for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")]
+    g = {k: np.empty(n) for k in ("n_e", "T_e", "T_i", "B", "H")}
+    gt = np.zeros(resid.size)
+    check(lib().rc_selftest_backward_host(ctypes.byref(spec), P(resid), P(coeffs), *[P(a) for a in arrs],
+                                          *[P(a) for a in fw], *[P(a) for a in ct], n, float(dt), ctypes.byref(opts),
+                                          *[P(g[k]) for k in ("n_e", "T_e", "T_i", "B", "H")], P(gt)))
+    return g, gt

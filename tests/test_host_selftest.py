@@ -131,3 +131,31 @@ def test_step_floor_branches_on_host(spec64, storage64, floor):
     assert np.array_equal(got["status"], ref["status"])
     assert np.max(rel_err(got["T_e_new"], ref["T_e_new"])) < 1e-9
     assert np.max(rel_err(got["T_i_new"], ref["T_i_new"])) < 1e-9
+
+
+def test_backward_matches_oracle_gradient_on_host(spec64, storage64, cells0_small):
+    """The per-cell adjoint (library source on the host) against the oracle's
+    implicit-function-theorem gradient on identical tables."""
+    from oracle import grad as Gd
+    resid, coeffs, stored = storage64
+    ts = S.TableSet(spec64, stored)
+    cells = {f: cells0_small[f][:1024] for f in W.FIELDS}
+    out = S.step_be(ts, *[cells[f] for f in W.FIELDS], DT)
+    rng = np.random.default_rng(5)
+    cot = {k: rng.normal(size=1024) for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")}
+    ref = Gd.vjp_step_be(ts, cells, out, DT, cot["T_e_new"], cot["T_i_new"], cot["Q_rad"], cot["Q_cc"])
+    fwd = {"T_e_new": out["T_e_new"], "T_i_new": out["T_i_new"], "status": out["status"]}
+    g, gt = R.selftest_backward_host(R.default_spec(64), resid, coeffs, cells, fwd, cot, DT)
+    # a gradient is only meaningful relative to the loss it differentiates:
+    # where d L / d ln p is below ~1e-12 of the loss terms (e.g. d/dB of a
+    # brem-dominated cell, flat in B up to table rounding) both sides hold noise
+    mag = (np.abs(cot["T_e_new"] * out["T_e_new"]) + np.abs(cot["T_i_new"] * out["T_i_new"])
+           + np.abs(cot["Q_rad"] * out["q_rad"]) + np.abs(cot["Q_cc"] * out["q_cc"]))
+    for f in W.FIELDS:
+        err = np.abs(g[f] - ref[f]) * cells[f]
+        assert np.all(err <= 1e-9 * np.abs(ref[f] * cells[f]) + 1e-12 * mag), f
+    vc = 64 ** 3
+    for k, name in enumerate(T.TABLE_NAMES):
+        want = ref["tables"][name].ravel()
+        got = gt[k * vc:(k + 1) * vc]
+        assert np.max(np.abs(got - want)) <= 1e-9 * np.max(np.abs(want)), name
