@@ -171,6 +171,49 @@ rc_status rc_tables_destroy(rc_tables t);
 rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n, double dt,
                        const rc_step_opts* opts, const rc_out* out, void* stream);
 
+/* One adaptive-mesh block of one accretion-rate state: cells first_cell ..
+ * first_cell + n_cells - 1 of the state and output arrays, advanced with
+ * dt_per_state[state_id]. */
+typedef struct {
+  int64_t first_cell;
+  int32_t n_cells;
+  int32_t state_id;
+} rc_block;
+
+#define RC_MAX_STATES 64
+
+/* Batched form: many uneven blocks and several states in one launch of a
+ * persistent kernel whose workgroups take blocks from an atomic work queue
+ * (every workgroup exits once the queue is drained).  blocks is a device array
+ * of n_blocks entries; blocks whose range lies outside [0, n_total) or whose
+ * state_id is outside [0, n_states) are skipped.  dt_per_state is a host array
+ * of n_states (1 .. RC_MAX_STATES) positive finite values.  Same per-cell
+ * semantics as rc_cool_step.  Uses an internal 4-byte device counter
+ * allocated on first use per table handle; calls that overlap on one table
+ * handle must use the same stream.  Asynchronous on stream. */
+rc_status rc_cool_step_batched(rc_tables t, const rc_state* state, int64_t n_total, const rc_block* blocks,
+                               int32_t n_blocks, const double* dt_per_state, int32_t n_states,
+                               const rc_step_opts* opts, const rc_out* out, void* stream);
+
+/* A captured launch plan for a fixed batched problem (the same buffers every
+ * replay): the counter reset (a one-thread kernel) and the persistent kernel,
+ * captured into a hipGraph and instantiated once.  With autotune != 0 the
+ * workgroup size (64, 128, 256) and the persistent grid (1, 2, 4 or 8
+ * workgroups per compute unit) are chosen by timing each candidate with HIP
+ * events on the given stream (the outputs are written during tuning).
+ * blocks is copied to the host once to validate every range (RC_EINVAL).
+ * The plan keeps pointers, not copies, of state, out and blocks. */
+typedef struct rc_plan_s* rc_plan;
+rc_status rc_plan_create(rc_tables t, const rc_state* state, int64_t n_total, const rc_block* blocks,
+                         int32_t n_blocks, const double* dt_per_state, int32_t n_states,
+                         const rc_step_opts* opts, const rc_out* out, int32_t autotune, void* stream,
+                         rc_plan* plan);
+/* Replay the plan's graph on stream (asynchronous). */
+rc_status rc_plan_launch(rc_plan plan, void* stream);
+/* Chosen launch shape and the tuned time of one launch (ms, 0 if not tuned). */
+rc_status rc_plan_info(rc_plan plan, int32_t* block, int32_t* grid, double* tuned_ms);
+rc_status rc_plan_destroy(rc_plan plan);
+
 /* Forward outputs the backward pass reads (device pointers, length n). */
 typedef struct {
   const double* T_e_new;

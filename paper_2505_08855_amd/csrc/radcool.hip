@@ -158,6 +158,7 @@ void destroy_tables(rc_tables_s* t) {
   release_textures(t);
   if (t->d_cool) (void)hipFree(t->d_cool);
   if (t->d_coul) (void)hipFree(t->d_coul);
+  if (t->d_counter) (void)hipFree(t->d_counter);
   t->magic = 0;
   delete t;
 }

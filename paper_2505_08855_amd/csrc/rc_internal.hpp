@@ -27,6 +27,7 @@ struct rc_tables_s {
   hipArray_t tex_arr[4] = {nullptr, nullptr, nullptr, nullptr};
   hipTextureObject_t tex[4] = {0, 0, 0, 0};
   bool tex_ready = false;
+  void* d_counter = nullptr;        // work-queue counter of the batched kernel (allocated on first use)
 };
 
 namespace rc {

@@ -99,8 +99,8 @@ template <class Tab>
 struct CellSolver {
   const Tab& tab;
   const StepParams& P;
-  // per-cell constants
-  double T_e, T_i, H, c, cS, tau_sca, invH, invH2;
+  // per-cell constants (dt is per cell so that batched work items can carry their own)
+  double T_e, T_i, H, c, cS, tau_sca, invH, invH2, dt;
   // gather coordinates that stay fixed during the solve
   int iN, iB, in_;
   double tN, tB, tn;
@@ -115,7 +115,8 @@ struct CellSolver {
   RC_HD CellSolver(const Tab& t, const StepParams& p) : tab(t), P(p) {}
 
   // per-cell constants and fixed coordinates; returns s0 = ln T_e
-  RC_HD double setup(double n_e, double te, double ti, double b, double h) {
+  RC_HD double setup(double n_e, double te, double ti, double b, double h, double dt_) {
+    dt = dt_;
     T_e = te;
     T_i = ti;
     H = h;
@@ -221,7 +222,6 @@ struct CellSolver {
   // [min(x, T_i), max(x, T_i)], where E2 changes sign; returns z and dz/dx.
   // *K_first receives v_c at the first trial z (the warm start).
   RC_HD double solve_z(double x, const Coord& ce, double zg, double* dzdx, double* K_first) {
-    const double dt = P.dt;
     double lo = fmin(x, T_i), hi = fmax(x, T_i);
     double z = fmin(fmax(zg, lo), hi);
     double K = 0.0, dlx = 0.0, dlz = 0.0;
@@ -258,7 +258,6 @@ struct CellSolver {
   // outer residual G = log1p([c (x - T_e) + c (z - T_i) + dt Q_rad(x)] / (c (T_e + T_i)))
   // at x = exp(s), its slope dG/ds, and (optionally) Q_rad(x) and v_c at the warm start
   RC_HD double outer(double s, double x, bool on, double* z, double* dG, double* q_out, double* K_first) {
-    const double dt = P.dt;
     const double lx = s * (1.0 / kLn10);
     double q, dq, dzdx;
     q_rad(x, lx, on, &q, &dq);
@@ -389,7 +388,6 @@ struct CellSolver {
   }
 
   RC_HD void explicit16(double s0, CellOut* o) {
-    const double dt = P.dt;
     const double h = dt / 16.0;
     double te = T_e, ti = T_i, lte = s0 * (1.0 / kLn10);
     for (int k = 0; k < 16; ++k) {
@@ -453,7 +451,7 @@ struct CellSolver {
 RC_HD bool bad_input(double v) { return !(v > 0.0) || !isfinite(v); }
 
 template <int SCHEME, class Tab>
-RC_HD void cool_cell(const Tab& tab, const StepParams& P, double n_e, double T_e, double T_i, double B,
+RC_HD void cool_cell(const Tab& tab, const StepParams& P, double dt, double n_e, double T_e, double T_i, double B,
                      double H, bool diag, CellOut* o) {
   if (bad_input(n_e) || bad_input(T_e) || bad_input(T_i) || bad_input(B) || bad_input(H)) {
     const double nan = __builtin_nan("");
@@ -462,7 +460,7 @@ RC_HD void cool_cell(const Tab& tab, const StepParams& P, double n_e, double T_e
     return;
   }
   CellSolver<Tab> cs(tab, P);
-  const double s0 = cs.setup(n_e, T_e, T_i, B, H);
+  const double s0 = cs.setup(n_e, T_e, T_i, B, H, dt);
   o->status = cs.clamp;
   if (SCHEME == SCHEME_NEWTON) {
     cs.newton(s0, o);
@@ -478,9 +476,9 @@ RC_HD void cool_cell(const Tab& tab, const StepParams& P, double n_e, double T_e
 template <class Tab>
 RC_HD void cool_cell_any(const Tab& tab, const StepParams& P, double n_e, double T_e, double T_i, double B,
                          double H, bool diag, CellOut* o) {
-  if (P.scheme == SCHEME_NEWTON) cool_cell<SCHEME_NEWTON>(tab, P, n_e, T_e, T_i, B, H, diag, o);
-  else if (P.scheme == SCHEME_EXPLICIT16) cool_cell<SCHEME_EXPLICIT16>(tab, P, n_e, T_e, T_i, B, H, diag, o);
-  else cool_cell<SCHEME_RATES>(tab, P, n_e, T_e, T_i, B, H, diag, o);
+  if (P.scheme == SCHEME_NEWTON) cool_cell<SCHEME_NEWTON>(tab, P, P.dt, n_e, T_e, T_i, B, H, diag, o);
+  else if (P.scheme == SCHEME_EXPLICIT16) cool_cell<SCHEME_EXPLICIT16>(tab, P, P.dt, n_e, T_e, T_i, B, H, diag, o);
+  else cool_cell<SCHEME_RATES>(tab, P, P.dt, n_e, T_e, T_i, B, H, diag, o);
 }
 
 // Table-free rates at the input state from the closed forms (DIRECT variant).

@@ -9,38 +9,9 @@
 
 #include "radcool.h"
 #include "rc_internal.hpp"
+#include "rc_kernels.hpp"
 
 namespace rc {
-
-struct StateArgs {
-  const double* n_e;
-  const double* T_e;
-  const double* T_i;
-  const double* B;
-  const double* H;
-};
-
-struct OutArgs {
-  double* T_e_new;
-  double* T_i_new;
-  double* Q_rad;
-  double* Q_cc;
-  double* Q_brem;
-  double* Q_syn;
-  double* eta;
-  uint8_t* status;
-};
-
-__device__ inline void store(const OutArgs& o, int64_t i, const CellOut& r) {
-  if (o.T_e_new) o.T_e_new[i] = r.T_e_new;
-  if (o.T_i_new) o.T_i_new[i] = r.T_i_new;
-  if (o.Q_rad) o.Q_rad[i] = r.q_rad;
-  if (o.Q_cc) o.Q_cc[i] = r.q_cc;
-  if (o.Q_brem) o.Q_brem[i] = r.q_brem;
-  if (o.Q_syn) o.Q_syn[i] = r.q_syn;
-  if (o.eta) o.eta[i] = r.eta;
-  if (o.status) o.status[i] = r.status;
-}
 
 template <int SCHEME, class Tab>
 __global__ __launch_bounds__(256) void k_step(Tab tab, StepParams P, StateArgs s, OutArgs o, int64_t n) {
@@ -48,7 +19,7 @@ __global__ __launch_bounds__(256) void k_step(Tab tab, StepParams P, StateArgs s
   if (i >= n) return;
   CellOut r;
   const bool diag = o.Q_brem || o.Q_syn || o.eta;
-  cool_cell<SCHEME>(tab, P, s.n_e[i], s.T_e[i], s.T_i[i], s.B[i], s.H[i], diag, &r);
+  cool_cell<SCHEME>(tab, P, P.dt, s.n_e[i], s.T_e[i], s.T_i[i], s.B[i], s.H[i], diag, &r);
   store(o, i, r);
 }
 

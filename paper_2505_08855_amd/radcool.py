@@ -28,7 +28,9 @@ EXPORTED = ("rc_default_spec", "rc_default_opts", "rc_build_tables", "rc_tables_
             "rc_tables_export", "rc_tables_info", "rc_tables_save", "rc_tables_load",
             "rc_tables_destroy", "rc_cool_step", "rc_constants", "rc_selftest_node_host",
             "rc_selftest_special_host", "rc_selftest_step_host", "rc_last_error",
-            "rc_cool_step_backward", "rc_selftest_backward_host")
+            "rc_cool_step_backward", "rc_selftest_backward_host", "rc_cool_step_batched",
+            "rc_plan_create", "rc_plan_launch", "rc_plan_info", "rc_plan_destroy")
+MAX_STATES = 64
 
 
 class RadcoolError(RuntimeError):
@@ -64,6 +66,13 @@ class Cotangent(ctypes.Structure):
 
 class Grad(ctypes.Structure):
     _fields_ = [(f, ctypes.c_void_p) for f in ("n_e", "T_e", "T_i", "B", "H", "tables")]
+
+
+class Block(ctypes.Structure):
+    _fields_ = [("first_cell", ctypes.c_int64), ("n_cells", ctypes.c_int32), ("state_id", ctypes.c_int32)]
+
+
+BLOCK_DTYPE = np.dtype([("first_cell", np.int64), ("n_cells", np.int32), ("state_id", np.int32)])
 
 
 class StepOpts(ctypes.Structure):
@@ -103,6 +112,11 @@ def lib():
             "rc_cool_step_backward": (i32, [vp, P(State), i64, dbl, P(StepOpts), P(Fwd), P(Cotangent), P(Grad), vp]),
             "rc_selftest_backward_host": (i32, [P(TableSpec), vp, vp] + [vp] * 12 + [i64, dbl, P(StepOpts)]
                                           + [vp] * 6),
+            "rc_cool_step_batched": (i32, [vp, P(State), i64, vp, i32, vp, i32, P(StepOpts), P(Out), vp]),
+            "rc_plan_create": (i32, [vp, P(State), i64, vp, i32, vp, i32, P(StepOpts), P(Out), i32, vp, P(vp)]),
+            "rc_plan_launch": (i32, [vp, vp]),
+            "rc_plan_info": (i32, [vp, P(i32), P(i32), P(dbl)]),
+            "rc_plan_destroy": (i32, [vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -291,6 +305,78 @@ def cool_step_backward(tables, state, dt, fwd, cot, opts=None, table_grad=None, 
     check(lib().rc_cool_step_backward(tables.handle, ctypes.byref(st), n, float(dt), ctypes.byref(opts),
                                       ctypes.byref(fw), ctypes.byref(ct), ctypes.byref(gr), _stream_ptr(stream)))
     return g
+
+
+def blocks_to_device(blocks, device):
+    """(first_cell, n_cells, state_id) triples -> a device buffer in rc_block layout."""
+    import torch
+    arr = np.array([tuple(b) for b in blocks], dtype=BLOCK_DTYPE)
+    return torch.from_numpy(arr.view(np.uint8).copy()).to(device), len(arr)
+
+
+def _out_struct(out):
+    return Out(*[out[k].data_ptr() if out.get(k) is not None else None
+                 for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc", "status", "Q_brem", "Q_syn", "eta")])
+
+
+def _alloc_out(n, dev):
+    import torch
+    out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")}
+    out["status"] = torch.empty(n, dtype=torch.uint8, device=dev)
+    return out
+
+
+def cool_step_batched(tables, state, blocks_dev, n_blocks, dt_per_state, opts=None, out=None, stream=None):
+    """Batched step over mesh blocks (device rc_block buffer from blocks_to_device)
+    with one dt per accretion state."""
+    n = _check_state(state)
+    opts = opts or default_opts()
+    out = out if out is not None else _alloc_out(n, state["n_e"].device)
+    dts = np.ascontiguousarray(dt_per_state, dtype=np.float64)
+    st = State(*[state[k].data_ptr() for k in ("n_e", "T_e", "T_i", "B", "H")])
+    check(lib().rc_cool_step_batched(tables.handle, ctypes.byref(st), n, ctypes.c_void_p(blocks_dev.data_ptr()),
+                                     n_blocks, dts.ctypes.data_as(ctypes.c_void_p), dts.size, ctypes.byref(opts),
+                                     ctypes.byref(_out_struct(out)), _stream_ptr(stream)))
+    return out
+
+
+class Plan:
+    """A captured (hipGraph) launch of the batched step on fixed buffers."""
+
+    def __init__(self, tables, state, blocks_dev, n_blocks, dt_per_state, opts=None, out=None, autotune=True,
+                 stream=None):
+        n = _check_state(state)
+        self.opts = opts or default_opts()
+        self.out = out if out is not None else _alloc_out(n, state["n_e"].device)
+        self._keep = (tables, state, blocks_dev)      # the plan holds pointers into these
+        dts = np.ascontiguousarray(dt_per_state, dtype=np.float64)
+        st = State(*[state[k].data_ptr() for k in ("n_e", "T_e", "T_i", "B", "H")])
+        h = ctypes.c_void_p()
+        check(lib().rc_plan_create(tables.handle, ctypes.byref(st), n, ctypes.c_void_p(blocks_dev.data_ptr()),
+                                   n_blocks, dts.ctypes.data_as(ctypes.c_void_p), dts.size, ctypes.byref(self.opts),
+                                   ctypes.byref(_out_struct(self.out)), 1 if autotune else 0, _stream_ptr(stream),
+                                   ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        check(lib().rc_plan_launch(self._h, _stream_ptr(stream)))
+        return self.out
+
+    def info(self):
+        b, g, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        check(lib().rc_plan_info(self._h, ctypes.byref(b), ctypes.byref(g), ctypes.byref(ms)))
+        return {"block": b.value, "grid": g.value, "tuned_ms": ms.value}
+
+    def destroy(self):
+        if self._h:
+            lib().rc_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def constants():
