@@ -22,32 +22,61 @@ struct BwdArgs {
   const uint8_t* status;
   const double *g_x, *g_z, *g_qr, *g_qc;
   double *o_n, *o_Te, *o_Ti, *o_B, *o_H, *o_tab;
+  double* g_se;           // scratch: gradient shared by the synch and eta entries
   int c1, c2, k1, k2;
   long vc;
   int newton;
+};
+
+// Table-gradient scatter with device atomics: brem and Coulomb straight into
+// the caller's array, the shared synch * eta gradient into library scratch
+// (added to both tables' slots by k_finish_se).
+struct AtomicScatter {
+  double* g_brem;
+  double* g_coul;
+  double* g_se;
+  __device__ void cool(const long* idx, const double* vb, const double* vse) const {
+    for (int k = 0; k < 8; ++k) {
+      if (vb[k] != 0.0) atomicAdd(g_brem + idx[k], vb[k]);
+      if (vse[k] != 0.0) atomicAdd(g_se + idx[k], vse[k]);
+    }
+  }
+  __device__ void coul(const long* idx, const double* vc) const {
+    for (int k = 0; k < 8; ++k)
+      if (vc[k] != 0.0) atomicAdd(g_coul + idx[k], vc[k]);
+  }
 };
 
 template <class Tab>
 __global__ __launch_bounds__(256) void k_backward(Tab tab, StepParams P, BwdArgs a, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double* tabg = a.o_tab;
-  const long vc = a.vc;
-  auto add = [tabg, vc](int k, long idx, double v) {
-    if (tabg) atomicAdd(tabg + (k < 3 ? k * vc : 3 * vc) + idx, v);
-  };
+  AtomicScatter sc{a.o_tab, a.o_tab ? a.o_tab + 3 * a.vc : nullptr, a.g_se};
   CellGrad g;
   const double x = a.newton ? a.x[i] : a.T_e[i];
   const double z = a.newton ? a.z[i] : a.T_i[i];
   const uint8_t st = a.status ? a.status[i] : (uint8_t)0;
   cell_vjp(tab, P, a.c1, a.c2, a.k1, a.k2, a.n_e[i], a.T_e[i], a.T_i[i], a.B[i], a.H[i], x, z, st,
            a.g_x ? a.g_x[i] : 0.0, a.g_z ? a.g_z[i] : 0.0, a.g_qr ? a.g_qr[i] : 0.0, a.g_qc ? a.g_qc[i] : 0.0,
-           a.newton != 0, &g, add);
+           a.newton != 0, a.o_tab != nullptr, &g, sc);
   if (a.o_n) a.o_n[i] = g.n_e;
   if (a.o_Te) a.o_Te[i] = g.T_e;
   if (a.o_Ti) a.o_Ti[i] = g.T_i;
   if (a.o_B) a.o_B[i] = g.B;
   if (a.o_H) a.o_H[i] = g.H;
+}
+
+__global__ void k_zero(double* p, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+// add the shared synch * eta gradient to both tables' slots
+__global__ void k_finish_se(double* g_tab, const double* g_se, long vc) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < vc; i += (long)gridDim.x * blockDim.x) {
+    const double v = g_se[i];
+    g_tab[vc + i] += v;
+    g_tab[2 * vc + i] += v;
+  }
 }
 
 }  // namespace rc
@@ -94,8 +123,19 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
   const int block = opts->block ? opts->block : 256;
   const int64_t grid = (n + block - 1) / block;
   if (grid > 0x7fffffffLL) return set_error(RC_EINVAL, "rc_cool_step_backward: n too large for one launch");
+  hipStream_t hs = (hipStream_t)stream;
+  a.g_se = nullptr;
+  if (a.o_tab) {
+    if (!t->d_gscratch) {
+      const hipError_t ae = hipMalloc(&t->d_gscratch, sizeof(double) * a.vc);
+      if (ae != hipSuccess) return hip_fail(ae, "hipMalloc(table-gradient scratch)");
+    }
+    a.g_se = (double*)t->d_gscratch;
+    hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, hs, a.g_se, a.vc);
+  }
   GlobalTab tab{t->d_cool, t->d_coul, t->spec.cool.n[1], t->spec.cool.n[2], t->spec.coul.n[1], t->spec.coul.n[2]};
-  hipLaunchKernelGGL(k_backward<GlobalTab>, dim3((unsigned)grid), dim3(block), 0, (hipStream_t)stream, tab, P, a, n);
+  hipLaunchKernelGGL(k_backward<GlobalTab>, dim3((unsigned)grid), dim3(block), 0, hs, tab, P, a, n);
+  if (a.o_tab) hipLaunchKernelGGL(k_finish_se, dim3(1024), dim3(256), 0, hs, a.o_tab, a.g_se, a.vc);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "rc_cool_step_backward launch");
   return RC_OK;
@@ -126,15 +166,26 @@ extern "C" rc_status rc_selftest_backward_host(const rc_table_spec* spec, const 
   std::vector<float4> cool((size_t)vc);
   for (long i = 0; i < vc; ++i) cool[i] = make_float4(resid[i], resid[vc + i], resid[2 * vc + i], 0.0f);
   GlobalTab tab{cool.data(), resid + 3 * vc, spec->cool.n[1], spec->cool.n[2], spec->coul.n[1], spec->coul.n[2]};
-  auto add = [g_tables, vc](int k, long idx, double v) {
-    if (g_tables) g_tables[(k < 3 ? k * vc : 3 * vc) + idx] += v;
-  };
+  struct HostScatter {
+    double* g;
+    long vc;
+    void cool(const long* idx, const double* vb, const double* vse) const {
+      for (int k = 0; k < 8; ++k) {
+        g[idx[k]] += vb[k];
+        g[vc + idx[k]] += vse[k];
+        g[2 * vc + idx[k]] += vse[k];
+      }
+    }
+    void coul(const long* idx, const double* vc_) const {
+      for (int k = 0; k < 8; ++k) g[3 * vc + idx[k]] += vc_[k];
+    }
+  } sc{g_tables, vc};
   for (int64_t i = 0; i < n; ++i) {
     CellGrad g;
     cell_vjp(tab, P, spec->cool.n[1], spec->cool.n[2], spec->coul.n[1], spec->coul.n[2], n_e[i], T_e[i], T_i[i],
              B[i], H[i], newton ? T_e_new[i] : T_e[i], newton ? T_i_new[i] : T_i[i], status ? status[i] : 0,
              cot_T_e_new ? cot_T_e_new[i] : 0.0, cot_T_i_new ? cot_T_i_new[i] : 0.0,
-             cot_Q_rad ? cot_Q_rad[i] : 0.0, cot_Q_cc ? cot_Q_cc[i] : 0.0, newton, &g, add);
+             cot_Q_rad ? cot_Q_rad[i] : 0.0, cot_Q_cc ? cot_Q_cc[i] : 0.0, newton, g_tables != nullptr, &g, sc);
     if (g_n_e) g_n_e[i] = g.n_e;
     if (g_T_e) g_T_e[i] = g.T_e;
     if (g_T_i) g_T_i[i] = g.T_i;

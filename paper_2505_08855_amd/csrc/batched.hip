@@ -11,6 +11,7 @@
 
 #include "radcool.h"
 #include "rc_internal.hpp"
+#include "rc_compact.hpp"
 #include "rc_kernels.hpp"
 
 namespace rc {
@@ -59,6 +60,31 @@ __global__ __launch_bounds__(256) void k_batched(Tab tab, StepParams P, StateArg
   }
 }
 
+// Newton scheme with in-workgroup compaction: each work item's cells are
+// processed in tiles of kTile (the workgroup size is fixed to kTile).
+template <class Tab>
+__global__ __launch_bounds__(kTile) void k_batched_compact(Tab tab, StepParams P, StateArgs s, OutArgs o, BatchArgs b) {
+  __shared__ ParkedTile L;
+  __shared__ int item;
+  const bool diag = o.Q_brem || o.Q_syn || o.eta;
+  for (;;) {
+    if (threadIdx.x == 0) item = (int)atomicAdd(b.counter, 1u);
+    __syncthreads();
+    const int w = item;
+    __syncthreads();
+    if (w >= b.n_blocks) break;
+    const rc_block blk = b.blocks[w];
+    if (blk.first_cell < 0 || blk.n_cells <= 0 || blk.first_cell > b.n_total - blk.n_cells || blk.state_id < 0 ||
+        blk.state_id >= b.n_states)
+      continue;
+    const double dt = b.dt[blk.state_id];
+    for (int k0 = 0; k0 < blk.n_cells; k0 += kTile) {
+      const int count = blk.n_cells - k0 < kTile ? blk.n_cells - k0 : kTile;
+      newton_tile(tab, P, dt, blk.first_cell + k0, count, s, o, diag, L);
+    }
+  }
+}
+
 namespace {
 
 rc_status check_batch_args(rc_tables t, const rc_state* state, int64_t n_total, const rc_block* blocks,
@@ -100,7 +126,9 @@ rc_status fill_scratch(void* scratch, const double* dts, int n_states, hipStream
 hipError_t launch_batched(int scheme, const GlobalTab& tab, const StepParams& P, const StateArgs& s, const OutArgs& o,
                           const BatchArgs& b, int block, int grid, hipStream_t hs) {
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, hs, b.counter);
-  if (scheme == RC_SCHEME_NEWTON)
+  if (scheme == RC_SCHEME_NEWTON && block == kTile)
+    hipLaunchKernelGGL(k_batched_compact<GlobalTab>, dim3(grid), dim3(kTile), 0, hs, tab, P, s, o, b);
+  else if (scheme == RC_SCHEME_NEWTON)
     hipLaunchKernelGGL((k_batched<SCHEME_NEWTON, GlobalTab>), dim3(grid), dim3(block), 0, hs, tab, P, s, o, b);
   else if (scheme == RC_SCHEME_EXPLICIT16)
     hipLaunchKernelGGL((k_batched<SCHEME_EXPLICIT16, GlobalTab>), dim3(grid), dim3(block), 0, hs, tab, P, s, o, b);

@@ -159,6 +159,7 @@ void destroy_tables(rc_tables_s* t) {
   if (t->d_cool) (void)hipFree(t->d_cool);
   if (t->d_coul) (void)hipFree(t->d_coul);
   if (t->d_counter) (void)hipFree(t->d_counter);
+  if (t->d_gscratch) (void)hipFree(t->d_gscratch);
   t->magic = 0;
   delete t;
 }

@@ -148,13 +148,17 @@ struct CellGrad {
   double n_e, T_e, T_i, B, H;
 };
 
-// Adjoint of one cell.  (x, z, status) are the forward outputs; add(k, idx, v)
-// accumulates v into the gradient of table k (0 brem, 1 synch, 2 eta, 3 coul)
-// at flat node index idx.
-template <class Tab, class Add>
+// Adjoint of one cell.  (x, z, status) are the forward outputs.  Table-entry
+// contributions go to sc.cool(idx[8], brem[8], synch_eta[8]) and
+// sc.coul(idx[8], coul[8]): the synchrotron and Compton tables enter only as
+// the product v_synch v_eta, so their log2 entries receive identical
+// gradients and are scattered once; when the solution and the input state
+// fall in the same table cell their corner contributions are merged first.
+template <class Tab, class Scatter>
 RC_HD void cell_vjp(const Tab& tab, const StepParams& P, int c1, int c2, int k1, int k2, double n_e, double T_e,
                     double T_i, double B, double H, double x, double z, unsigned char status, double g_x,
-                    double g_z, double g_qr, double g_qc, bool newton, CellGrad* out, Add add) {
+                    double g_z, double g_qr, double g_qc, bool newton, bool want_tables, CellGrad* out,
+                    Scatter& sc) {
   out->n_e = out->T_e = out->T_i = out->B = out->H = 0.0;
   if (status & ST_INVALID) return;
   const double dt = P.dt;
@@ -162,16 +166,22 @@ RC_HD void cell_vjp(const Tab& tab, const StepParams& P, int c1, int c2, int k1,
   const double c_n = kUperNKT * kKB;
   const double lne = log10(n_e), lH = log10(H), lB = log10(B);
   double gn = 0.0, gTe = 0.0, gTi = 0.0, gB = 0.0, gH = 0.0;
+  // corner coefficients of the two evaluation points (solution, input)
+  double cb[2] = {0.0, 0.0}, cse[2] = {0.0, 0.0}, cc[2] = {0.0, 0.0};
+  CoolPoint cp[2];
+  CoulPoint kp[2];
+  bool have[2] = {false, false};
   if (newton) {
     const bool floor = (status & ST_FLOOR) != 0;
     const double lx = log10(x), lz = log10(z);
-    const CoolPoint cp = cool_point(tab, P, lne + lH, lx, lB, c1, c2);
-    const CoulPoint kp = coul_point(tab, P, lne, lx, lz, k1, k2);
-    const QradPartials qp = qrad_partials(cp, n_e, x, B, H, x >= P.T_floor);
-    const double kc = exp2(kp.y);
-    const double kn = kLn2 * kc * kp.dy[0] / (n_e * kLn10);
-    const double kx = kLn2 * kc * kp.dy[1] / (x * kLn10);
-    const double kz = kLn2 * kc * kp.dy[2] / (z * kLn10);
+    cp[0] = cool_point(tab, P, lne + lH, lx, lB, c1, c2);
+    kp[0] = coul_point(tab, P, lne, lx, lz, k1, k2);
+    have[0] = true;
+    const QradPartials qp = qrad_partials(cp[0], n_e, x, B, H, x >= P.T_floor);
+    const double kc = exp2(kp[0].y);
+    const double kn = kLn2 * kc * kp[0].dy[0] / (n_e * kLn10);
+    const double kx = kLn2 * kc * kp[0].dy[1] / (x * kLn10);
+    const double kz = kLn2 * kc * kp[0].dy[2] / (z * kLn10);
     const double zx = z - x;
     const double j11 = c + dt * qp.dx + dt * kc - dt * zx * kx;
     const double j12 = -dt * kc - dt * zx * kz;
@@ -191,50 +201,77 @@ RC_HD void cell_vjp(const Tab& tab, const StepParams& P, int c1, int c2, int k1,
     gTi = l2 * c;
     gB = -l1 * dt * qp.dB;
     gH = -l1 * dt * qp.dH;
-    const double a_b = -l1 * dt * qp.sb, a_se = -l1 * dt * qp.sse;
-    const double a_c = (l1 - l2) * dt * zx * kLn2 * kc;
-    for (int k = 0; k < 8; ++k) {
-      if (a_b != 0.0) add(0, cp.idx[k], a_b * cp.w[k]);
-      if (a_se != 0.0) {
-        add(1, cp.idx[k], a_se * cp.w[k]);
-        add(2, cp.idx[k], a_se * cp.w[k]);
-      }
-      if (a_c != 0.0) add(3, kp.idx[k], a_c * kp.w[k]);
-    }
+    cb[0] = -l1 * dt * qp.sb;
+    cse[0] = -l1 * dt * qp.sse;
+    cc[0] = (l1 - l2) * dt * zx * kLn2 * kc;
   } else {
     gTe = g_x;    // rates only: T' = T
     gTi = g_z;
   }
   if (g_qr != 0.0 || g_qc != 0.0) {
     const double lte = log10(T_e), lti = log10(T_i);
-    const CoolPoint cp = cool_point(tab, P, lne + lH, lte, lB, c1, c2);
-    const CoulPoint kp = coul_point(tab, P, lne, lte, lti, k1, k2);
-    const QradPartials qp = qrad_partials(cp, n_e, T_e, B, H, T_e >= P.T_floor);
-    const double kc = exp2(kp.y);
-    const double kn = kLn2 * kc * kp.dy[0] / (n_e * kLn10);
-    const double kx = kLn2 * kc * kp.dy[1] / (T_e * kLn10);
-    const double kz = kLn2 * kc * kp.dy[2] / (T_i * kLn10);
+    cp[1] = cool_point(tab, P, lne + lH, lte, lB, c1, c2);
+    kp[1] = coul_point(tab, P, lne, lte, lti, k1, k2);
+    have[1] = true;
+    const QradPartials qp = qrad_partials(cp[1], n_e, T_e, B, H, T_e >= P.T_floor);
+    const double kc = exp2(kp[1].y);
+    const double kn = kLn2 * kc * kp[1].dy[0] / (n_e * kLn10);
+    const double kx = kLn2 * kc * kp[1].dy[1] / (T_e * kLn10);
+    const double kz = kLn2 * kc * kp[1].dy[2] / (T_i * kLn10);
     const double gap = T_i - T_e;
     gn += g_qr * qp.dn + g_qc * gap * kn;
     gTe += g_qr * qp.dx + g_qc * (-kc + gap * kx);
     gTi += g_qc * (kc + gap * kz);
     gB += g_qr * qp.dB;
     gH += g_qr * qp.dH;
-    const double a_b = g_qr * qp.sb, a_se = g_qr * qp.sse, a_c = g_qc * gap * kLn2 * kc;
-    for (int k = 0; k < 8; ++k) {
-      if (a_b != 0.0) add(0, cp.idx[k], a_b * cp.w[k]);
-      if (a_se != 0.0) {
-        add(1, cp.idx[k], a_se * cp.w[k]);
-        add(2, cp.idx[k], a_se * cp.w[k]);
-      }
-      if (a_c != 0.0) add(3, kp.idx[k], a_c * kp.w[k]);
-    }
+    cb[1] = g_qr * qp.sb;
+    cse[1] = g_qr * qp.sse;
+    cc[1] = g_qc * gap * kLn2 * kc;
   }
   out->n_e = gn;
   out->T_e = gTe;
   out->T_i = gTi;
   out->B = gB;
   out->H = gH;
+  if (!want_tables) return;
+  // cooling tables
+  {
+    double vb[8], vse[8];
+    if (have[0] && have[1] && cp[0].idx[0] == cp[1].idx[0]) {
+      if (cb[0] != 0.0 || cse[0] != 0.0 || cb[1] != 0.0 || cse[1] != 0.0) {
+        for (int k = 0; k < 8; ++k) {
+          vb[k] = cb[0] * cp[0].w[k] + cb[1] * cp[1].w[k];
+          vse[k] = cse[0] * cp[0].w[k] + cse[1] * cp[1].w[k];
+        }
+        sc.cool(cp[0].idx, vb, vse);
+      }
+    } else {
+      for (int p = 0; p < 2; ++p) {
+        if (!have[p] || (cb[p] == 0.0 && cse[p] == 0.0)) continue;
+        for (int k = 0; k < 8; ++k) {
+          vb[k] = cb[p] * cp[p].w[k];
+          vse[k] = cse[p] * cp[p].w[k];
+        }
+        sc.cool(cp[p].idx, vb, vse);
+      }
+    }
+  }
+  // Coulomb table
+  {
+    double vc[8];
+    if (have[0] && have[1] && kp[0].idx[0] == kp[1].idx[0]) {
+      if (cc[0] != 0.0 || cc[1] != 0.0) {
+        for (int k = 0; k < 8; ++k) vc[k] = cc[0] * kp[0].w[k] + cc[1] * kp[1].w[k];
+        sc.coul(kp[0].idx, vc);
+      }
+    } else {
+      for (int p = 0; p < 2; ++p) {
+        if (!have[p] || cc[p] == 0.0) continue;
+        for (int k = 0; k < 8; ++k) vc[k] = cc[p] * kp[p].w[k];
+        sc.coul(kp[p].idx, vc);
+      }
+    }
+  }
 }
 
 }  // namespace rc

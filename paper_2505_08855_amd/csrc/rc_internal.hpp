@@ -28,6 +28,7 @@ struct rc_tables_s {
   hipTextureObject_t tex[4] = {0, 0, 0, 0};
   bool tex_ready = false;
   void* d_counter = nullptr;        // work-queue counter of the batched kernel (allocated on first use)
+  void* d_gscratch = nullptr;       // backward: synch * eta table-gradient accumulator (first use)
 };
 
 namespace rc {

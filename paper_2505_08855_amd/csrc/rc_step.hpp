@@ -95,6 +95,15 @@ struct CellOut {
   unsigned char status;
 };
 
+// Iteration state of the backward-Euler Newton solve: current iterate s =
+// ln T_e' with its residual G and slope dG, the ion temperature z solved
+// there, the sign bracket [lo, hi] in s, the pending evaluation point
+// (kind, se, xe) and flags.
+struct NewtonState {
+  double s, G, dG, z, lo, hi, se, xe, z_floor;
+  int kind, iters, flags;
+};
+
 template <class Tab>
 struct CellSolver {
   const Tab& tab;
@@ -270,120 +279,137 @@ struct CellSolver {
   }
 
   // Newton driver.  Every evaluation of the outer residual goes through one
-  // call site (a small state machine picks the next point), so the inlined
-  // rate code exists once in the kernel.
-  RC_HD void newton(double s0, CellOut* o) {
-    enum { FIRST, ITER, PROBE_ON, PROBE_OFF, FINAL };
+  // call site (newton_round: evaluate at the pending point, then choose the
+  // next one), so the inlined rate code exists once in the kernel; the whole
+  // iteration state lives in NewtonState so that a kernel can also park a cell
+  // between rounds (in-workgroup compaction).
+  enum { FIRST = 0, ITER = 1, PROBE_ON = 2, PROBE_OFF = 3, FINAL = 4 };
+  enum { F_LO_KNOWN = 1, F_FLOOR_PENDING = 2, F_HEATING = 4, F_ON = 8 };
+
+  RC_HD void newton_begin(double s0, NewtonState& ns) const {
+    ns.s = s0; ns.G = 0.0; ns.dG = 1.0; ns.z = T_i;
+    ns.lo = 0.0; ns.hi = 0.0;
+    ns.z_floor = T_i;
+    ns.kind = FIRST; ns.iters = 0;
+    ns.se = s0; ns.xe = T_e;
+    ns.flags = (T_e >= P.T_floor) ? F_ON : 0;
+  }
+
+  // one evaluation at the pending point; returns true when the cell is done
+  // (T_e_new, T_i_new and the FLOOR / MAXITER bits are then in o)
+  RC_HD bool newton_round(NewtonState& ns, CellOut* o) {
     const double T_floor = P.T_floor;
     const double sf = log(T_floor);
     const double tol = P.tol;
-    const double step_tol = sqrt(tol);
-    // current iterate and its residual; bracket in s with G(lo) < 0 < G(hi)
-    double s = s0, G = 0.0, dG = 1.0, z = T_i;
-    double lo = 0.0, hi = 0.0;
-    bool lo_known = false;
-    bool floor_pending = false;   // a descent may still have to stop on the floor
-    bool heating = false;
-    double z_floor = T_i;         // ion temperature solved at the floor (projection)
-    // next evaluation point
-    int kind = FIRST;
-    double se = s0, xe = T_e;
-    bool on = T_e >= T_floor;
-    int iters = 0;
-    for (;;) {
-      double ze = z, dGe, q, Kf;
-      const double Ge = outer(se, xe, on, &ze, &dGe, &q, &Kf);
-      bool propose = false;
-      if (kind == FINAL) {
-        o->T_e_new = xe;
-        o->T_i_new = ze;
-        return;
-      } else if (kind == FIRST) {
-        o->q_rad = q;
-        o->q_cc = (T_i - T_e) * Kf;
-        s = s0; G = Ge; dG = dGe; z = ze;
-        if (G == 0.0) { o->T_e_new = T_e; o->T_i_new = z; return; }
-        if (G > 0.0) {
-          hi = s0;
-          lo = log(fmin(T_i, T_floor));
-          floor_pending = on;
-          lo_known = !on;          // below the floor G(T_i) < 0 is guaranteed
-          propose = true;
-        } else {
-          heating = true;
-          lo = s0; lo_known = true;
-          hi = log(T_i);           // G(T_i) >= 0
-          if (T_e < T_floor && T_floor < T_i) {
-            // the floor lies inside the bracket: probe it with cooling off first
-            kind = PROBE_OFF; se = sf; xe = T_floor; on = false;
-          } else {
-            propose = true;
-          }
-        }
-      } else if (kind == PROBE_ON) {
-        z_floor = ze;
-        if (Ge < 0.0) {            // root above the floor
-          lo = sf; lo_known = true;
-          s = sf; G = Ge; dG = dGe; z = ze;
-          propose = true;
-        } else if (!heating && T_i < T_floor) {
-          // the root can also lie under the floor, where cooling is off
-          kind = PROBE_OFF; se = sf; xe = T_floor; on = false;
-        } else {
-          o->T_e_new = T_floor; o->T_i_new = ze; o->status |= ST_FLOOR;
-          return;
-        }
-      } else if (kind == PROBE_OFF) {
-        if (heating) {
-          if (Ge >= 0.0) {         // root below the floor, cooling off
-            hi = sf;
-            propose = true;
-          } else {
-            kind = PROBE_ON; se = sf; xe = T_floor; on = true;
-          }
-        } else if (Ge > 0.0) {     // descent continues under the floor
-          hi = sf; lo = log(T_i); lo_known = true;
-          s = sf; G = Ge; dG = dGe; z = ze;
-          propose = true;
-        } else {
-          o->T_e_new = T_floor; o->T_i_new = z_floor; o->status |= ST_FLOOR;
-          return;
-        }
-      } else {  // ITER
-        s = se; G = Ge; dG = dGe; z = ze;
-        if (G > 0.0) hi = s;
-        else if (G < 0.0) { lo = s; lo_known = true; }
-        if (G == 0.0 || (lo_known && (hi - lo) <= tol)) { o->T_e_new = xe; o->T_i_new = z; return; }
-        if (++iters >= P.max_iter) {
-          o->status |= ST_MAXITER;
-          o->T_e_new = xe; o->T_i_new = z;
-          return;
-        }
+    double ze = ns.z, dGe, q, Kf;
+    const double Ge = outer(ns.se, ns.xe, (ns.flags & F_ON) != 0, &ze, &dGe, &q, &Kf);
+    const int kind = ns.kind;
+    bool propose = false;
+    if (kind == FINAL) {
+      o->T_e_new = ns.xe;
+      o->T_i_new = ze;
+      return true;
+    } else if (kind == FIRST) {
+      o->q_rad = q;
+      o->q_cc = (T_i - T_e) * Kf;
+      ns.G = Ge; ns.dG = dGe; ns.z = ze;
+      if (ns.G == 0.0) { o->T_e_new = T_e; o->T_i_new = ze; return true; }
+      const bool on0 = (ns.flags & F_ON) != 0;
+      if (ns.G > 0.0) {
+        ns.hi = ns.s;
+        ns.lo = log(fmin(T_i, T_floor));
+        if (on0) ns.flags |= F_FLOOR_PENDING;
+        else ns.flags |= F_LO_KNOWN;          // below the floor G(T_i) < 0 is guaranteed
         propose = true;
+      } else {
+        ns.flags |= F_HEATING | F_LO_KNOWN;
+        ns.lo = ns.s;
+        ns.hi = log(T_i);                      // G(T_i) >= 0
+        if (T_e < T_floor && T_floor < T_i) {
+          // the floor lies inside the bracket: probe it with cooling off first
+          ns.kind = PROBE_OFF; ns.se = sf; ns.xe = T_floor; ns.flags &= ~F_ON;
+        } else {
+          propose = true;
+        }
       }
-      if (propose) {
-        double sn = s - G / dG;
-        const bool newton_ok = (dG > 0.0) && (sn == sn);
-        if (newton_ok && fabs(sn - s) <= step_tol && !(floor_pending && sn < sf)) {
-          // converged: Newton converges quadratically, so once the step is
-          // below sqrt(tol) the error left after taking it is O(tol); only
-          // z(x) remains to be solved at the new point.  Tested before the
-          // bracket safeguard, which could reject a step below an end's ulp.
-          kind = FINAL; se = sn; xe = exp(sn); on = false;
-          continue;
-        }
-        if (floor_pending && (!newton_ok || sn < sf)) {
-          // the descent would cross the floor (decided on the raw Newton step:
-          // the safeguard below only halves towards it): probe G just above it
-          floor_pending = false;
-          kind = PROBE_ON; se = sf; xe = T_floor; on = true;
-          continue;
-        }
-        if (!newton_ok || sn >= hi || (lo_known ? sn <= lo : sn < lo)) {
-          sn = lo_known ? 0.5 * (lo + hi) : 0.5 * (lo + s);
-        }
-        kind = ITER; se = sn; xe = exp(sn); on = xe >= T_floor;
+    } else if (kind == PROBE_ON) {
+      ns.z_floor = ze;
+      if (Ge < 0.0) {                          // root above the floor
+        ns.lo = sf; ns.flags |= F_LO_KNOWN;
+        ns.s = sf; ns.G = Ge; ns.dG = dGe; ns.z = ze;
+        propose = true;
+      } else if (!(ns.flags & F_HEATING) && T_i < T_floor) {
+        // the root can also lie under the floor, where cooling is off
+        ns.kind = PROBE_OFF; ns.se = sf; ns.xe = T_floor; ns.flags &= ~F_ON;
+      } else {
+        o->T_e_new = T_floor; o->T_i_new = ze; o->status |= ST_FLOOR;
+        return true;
       }
+    } else if (kind == PROBE_OFF) {
+      if (ns.flags & F_HEATING) {
+        if (Ge >= 0.0) {                       // root below the floor, cooling off
+          ns.hi = sf;
+          propose = true;
+        } else {
+          ns.kind = PROBE_ON; ns.se = sf; ns.xe = T_floor; ns.flags |= F_ON;
+        }
+      } else if (Ge > 0.0) {                   // descent continues under the floor
+        ns.hi = sf; ns.lo = log(T_i); ns.flags |= F_LO_KNOWN;
+        ns.s = sf; ns.G = Ge; ns.dG = dGe; ns.z = ze;
+        propose = true;
+      } else {
+        o->T_e_new = T_floor; o->T_i_new = ns.z_floor; o->status |= ST_FLOOR;
+        return true;
+      }
+    } else {  // ITER
+      ns.s = ns.se; ns.G = Ge; ns.dG = dGe; ns.z = ze;
+      if (ns.G > 0.0) ns.hi = ns.s;
+      else if (ns.G < 0.0) { ns.lo = ns.s; ns.flags |= F_LO_KNOWN; }
+      if (ns.G == 0.0 || ((ns.flags & F_LO_KNOWN) && (ns.hi - ns.lo) <= tol)) {
+        o->T_e_new = ns.xe; o->T_i_new = ze;
+        return true;
+      }
+      if (++ns.iters >= P.max_iter) {
+        o->status |= ST_MAXITER;
+        o->T_e_new = ns.xe; o->T_i_new = ze;
+        return true;
+      }
+      propose = true;
+    }
+    if (propose) {
+      const double s = ns.s, lo = ns.lo, hi = ns.hi;
+      const bool lo_known = (ns.flags & F_LO_KNOWN) != 0;
+      const bool floor_pending = (ns.flags & F_FLOOR_PENDING) != 0;
+      double sn = s - ns.G / ns.dG;
+      const bool newton_ok = (ns.dG > 0.0) && (sn == sn);
+      if (newton_ok && fabs(sn - s) <= sqrt(tol) && !(floor_pending && sn < sf)) {
+        // converged: Newton converges quadratically, so once the step is
+        // below sqrt(tol) the error left after taking it is O(tol); only
+        // z(x) remains to be solved at the new point.  Tested before the
+        // bracket safeguard, which could reject a step below an end's ulp.
+        ns.kind = FINAL; ns.se = sn; ns.xe = exp(sn); ns.flags &= ~F_ON;
+        return false;
+      }
+      if (floor_pending && (!newton_ok || sn < sf)) {
+        // the descent would cross the floor (decided on the raw Newton step:
+        // the safeguard below only halves towards it): probe G just above it
+        ns.flags &= ~F_FLOOR_PENDING;
+        ns.kind = PROBE_ON; ns.se = sf; ns.xe = T_floor; ns.flags |= F_ON;
+        return false;
+      }
+      if (!newton_ok || sn >= hi || (lo_known ? sn <= lo : sn < lo)) {
+        sn = lo_known ? 0.5 * (lo + hi) : 0.5 * (lo + s);
+      }
+      ns.kind = ITER; ns.se = sn; ns.xe = exp(sn);
+      if (ns.xe >= T_floor) ns.flags |= F_ON; else ns.flags &= ~F_ON;
+    }
+    return false;
+  }
+
+  RC_HD void newton(double s0, CellOut* o) {
+    NewtonState ns;
+    newton_begin(s0, ns);
+    while (!newton_round(ns, o)) {
     }
   }
 

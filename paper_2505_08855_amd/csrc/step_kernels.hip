@@ -9,6 +9,7 @@
 
 #include "radcool.h"
 #include "rc_internal.hpp"
+#include "rc_compact.hpp"
 #include "rc_kernels.hpp"
 
 namespace rc {
@@ -21,6 +22,17 @@ __global__ __launch_bounds__(256) void k_step(Tab tab, StepParams P, StateArgs s
   const bool diag = o.Q_brem || o.Q_syn || o.eta;
   cool_cell<SCHEME>(tab, P, P.dt, s.n_e[i], s.T_e[i], s.T_i[i], s.B[i], s.H[i], diag, &r);
   store(o, i, r);
+}
+
+// Newton with in-workgroup compaction: one tile of kTile cells per workgroup
+template <class Tab>
+__global__ __launch_bounds__(kTile) void k_newton_compact(Tab tab, StepParams P, StateArgs s, OutArgs o, int64_t n) {
+  __shared__ ParkedTile L;
+  const int64_t first = (int64_t)blockIdx.x * kTile;
+  const int64_t left = n - first;
+  const int count = left < kTile ? (int)left : kTile;
+  const bool diag = o.Q_brem || o.Q_syn || o.eta;
+  newton_tile(tab, P, P.dt, first, count, s, o, diag, L);
 }
 
 __global__ __launch_bounds__(256) void k_direct(StepParams P, StateArgs s, OutArgs o, int64_t n) {
@@ -96,7 +108,10 @@ extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n,
     hipLaunchKernelGGL(k_direct, dim3((unsigned)grid), dim3(block), 0, hs, P, s, o, n);
   } else {
     GlobalTab tab{t->d_cool, t->d_coul, t->spec.cool.n[1], t->spec.cool.n[2], t->spec.coul.n[1], t->spec.coul.n[2]};
-    if (opts->scheme == RC_SCHEME_NEWTON)
+    if (opts->scheme == RC_SCHEME_NEWTON && opts->block == 0)
+      hipLaunchKernelGGL(k_newton_compact<GlobalTab>, dim3((unsigned)((n + kTile - 1) / kTile)), dim3(kTile), 0, hs,
+                         tab, P, s, o, n);
+    else if (opts->scheme == RC_SCHEME_NEWTON)
       hipLaunchKernelGGL((k_step<SCHEME_NEWTON, GlobalTab>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, n);
     else if (opts->scheme == RC_SCHEME_EXPLICIT16)
       hipLaunchKernelGGL((k_step<SCHEME_EXPLICIT16, GlobalTab>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, n);

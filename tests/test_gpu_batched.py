@@ -53,12 +53,21 @@ def eager_reference(pb, dev):
     return ref
 
 
+def close(a, b):
+    """Same per-cell steps in different kernels: equal up to how multiply-adds
+    were fused; status bytes exactly."""
+    a = {k: v.cpu().numpy() for k, v in a.items()}
+    b = {k: v.cpu().numpy() for k, v in b.items()}
+    assert np.array_equal(a["status"], b["status"])
+    for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc"):
+        assert np.max(rel_err(a[k], b[k])) < 1e-12, k
+
+
 def test_batched_equals_plain_step_per_state(dev, problem):
     ref = eager_reference(problem, dev)
     out = R.cool_step_batched(problem["tables"], problem["state"], problem["bdev"], problem["nb"], problem["dts"])
     torch.cuda.synchronize()
-    for k in ref:
-        assert torch.equal(out[k], ref[k]), k
+    close(out, ref)
 
 
 def test_batched_against_oracle_samples(dev, problem):
@@ -87,8 +96,12 @@ def test_plan_graph_replays(dev, problem):
         # eager work between replays
         junk = torch.randn(1 << 20, device=dev).sum().item()
         assert junk == junk
-        for k in ref:
-            assert torch.equal(plan.out[k], ref[k]), (rep, k)
+        close(plan.out, ref)
+        if rep == 0:
+            first = {k: v.clone() for k, v in plan.out.items()}
+        else:
+            for k in first:                       # replays of one graph are bitwise identical
+                assert torch.equal(plan.out[k], first[k]), (rep, k)
     plan.destroy()
 
 

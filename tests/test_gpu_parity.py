@@ -278,3 +278,20 @@ def test_full_size_iid256_sampled(dev, oracle128):
     resid_e = (lost - DT * q_new).abs() / (c * (st["T_e"] + st["T_i"]))
     assert float(resid_e[~floor].max()) < 1e-9
     assert int((out["status"] & R.ST_MAXITER).sum()) == 0
+
+
+def test_compacted_newton_equals_plain_kernel(dev, imported64):
+    """The default Newton kernel parks unfinished cells in LDS between rounds
+    (in-workgroup compaction); a plain one-cell-per-thread launch (explicit
+    block size) runs the same per-cell steps.  Multiply-adds may be fused
+    differently in the two kernels, so values agree to rounding, and a cell
+    parked in the wrong slot would show up as a gross mismatch."""
+    gt, _ = imported64
+    cells = W.workload(3, n=100_003)
+    st = to_dev(cells, dev)
+    a = {k: v.cpu().numpy() for k, v in R.cool_step(gt, st, DT, R.default_opts(), diagnostics=True).items()}
+    b = {k: v.cpu().numpy() for k, v in R.cool_step(gt, st, DT, R.default_opts(block=256),
+                                                     diagnostics=True).items()}
+    assert np.array_equal(a["status"], b["status"])
+    for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc", "Q_brem", "Q_syn", "eta"):
+        assert np.max(rel_err(a[k], b[k])) < 1e-12, k
