@@ -8,19 +8,36 @@ the closed forms, one backward-Euler (Newton) cooling step per timed step over
 all cells with dt = 1e-3 r_g/c (M = 10 M_sun).  Inputs and outputs stay in HBM.
 Prints one JSON line.
 
-Roofline: algorithmic HBM bytes per launch = 72 B per cell (read n_e, T_e, T_i,
+Roofline: algorithmic HBM bytes per step = 72 B per cell (read n_e, T_e, T_i,
 B, H as FP64; write T_e', T_i', Q_rad, Q_cc as FP64) + one read of the four
-tables; the status byte (1 B/cell) is counted too.  Achieved = bytes / average
-launch time from HIP events on the launch stream; peak = 8 TB/s.
+tables; the status byte (1 B/cell) is counted too.  A Newton step is one
+rc_cool_step call: a counter reset and the deferral launches (the first over
+all cells, the later ones over the queued stragglers).  Achieved = bytes /
+average step time from HIP events on the launch stream; peak = 8 TB/s.
+traffic: HBM bytes per step from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
+scaled by a plain 512 MiB copy's readings, taken from the committed counter
+summary when it was measured on the current kernel sources (else null).
 
 cpu_baseline: the oracle (oracle/, NumPy FP64, one process) timed on a seeded
 sample of the same workload; the same run supplies the max relative error of
 the GPU outputs on that sample.
+
+precision: the storage-precision experiment on a sample of the spherical
+workload with 64^3 tables: FP32 and bfloat16 residual storage, per-field
+errors against the oracle's FP64 tables, and the throughput of each.
+
+    python bench.py --counters FETCH_DIR WRITE_DIR
+turns two rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE; each run
+with --calibrate-copy) into the counter summary kept under profiles/.
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -31,6 +48,81 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = 5 * 8 + 4 * 8 + 1      # state in, T', Q_rad, Q_cc out, status
+COPY_BYTES = 64 << 23                   # the calibration copy: 512 MiB read and written
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "newton_iid256_t128_counters.md")
+STEP_KERNELS = re.compile(r"k_newton_phase<rc::GlobalTab,|k_zero_counts")   # demangled names, FP32 tables
+
+
+def source_hash():
+    """Hash of the library sources and build flags (identifies the kernels)."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2505_08855_amd", "csrc", "*.h*")))
+    files += [os.path.join(ROOT, "include", "radcool.h"), os.path.join(ROOT, "paper_2505_08855_amd", "build.py")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_counters(folder, counter):
+    """{kernel name: [value per dispatch]} of one rocprofv3 --pmc output folder (KiB)."""
+    out = {}
+    for path in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] == counter:
+                    out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def counters_summary(fetch_dir, write_dir):
+    """Markdown summary of the FETCH_SIZE / WRITE_SIZE passes with the traffic record."""
+    fetch = read_counters(fetch_dir, "FETCH_SIZE")
+    write = read_counters(write_dir, "WRITE_SIZE")
+    copy = [k for k in fetch if "copyBuffer" in k]
+    if not copy:
+        raise SystemExit("no copy kernel in the FETCH pass: run it with --calibrate-copy")
+    f_copy = np.mean(fetch[copy[0]]) * 1024.0
+    w_copy = np.mean(write[copy[0]]) * 1024.0
+    f_scale, w_scale = COPY_BYTES / f_copy, COPY_BYTES / w_copy
+
+    def per_step(table):
+        first = [k for k in table if "k_newton_phase<rc::GlobalTab, true, false>" in k]
+        steps = len(table[first[0]]) if first else 0
+        total = sum(sum(v) for k, v in table.items() if STEP_KERNELS.search(k)) * 1024.0
+        return total / max(steps, 1), steps
+
+    f_step, nf = per_step(fetch)
+    w_step, nw = per_step(write)
+    rec = {"source_hash": source_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
+           "fetch_bytes_per_step": f_step * f_scale, "write_bytes_per_step": w_step * w_scale,
+           "traffic_bytes_per_step": f_step * f_scale + w_step * w_scale, "steps_counted": [nf, nw]}
+    lines = ["| kernel | dispatches | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch |", "|---|---|---|---|"]
+    for k in sorted(set(fetch) | set(write)):
+        fv, wv = fetch.get(k, []), write.get(k, [])
+        lines.append("| %s | %d | %.6g | %.6g |" % (k[:90], max(len(fv), len(wv)), np.mean(fv) if fv else float("nan"),
+                                                   np.mean(wv) if wv else float("nan")))
+    print("\n".join(lines))
+    print()
+    print("Calibration (512 MiB device copy): FETCH_SIZE x %.4f, WRITE_SIZE x %.4f." % (f_scale, w_scale))
+    print("Per Newton step (all its launches): FETCH %.4g B, WRITE %.4g B, traffic %.4g B." %
+          (rec["fetch_bytes_per_step"], rec["write_bytes_per_step"], rec["traffic_bytes_per_step"]))
+    print()
+    print("traffic-record: " + json.dumps(rec))
+
+
+def measured_traffic():
+    """Traffic per step from the committed counter summary, if it matches these sources."""
+    try:
+        with open(TRAFFIC_SUMMARY) as fh:
+            m = re.search(r"^traffic-record: (\{.*\})$", fh.read(), re.M)
+    except OSError:
+        return None
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    return rec["traffic_bytes_per_step"] if rec.get("source_hash") == source_hash() else None
 
 
 def parse():
@@ -42,11 +134,14 @@ def parse():
     p.add_argument("--table-n", type=int, default=128)
     p.add_argument("--variant", default="auto")
     p.add_argument("--scheme", default="newton")
-    p.add_argument("--sample", type=int, default=16384, help="cells in the cpu_baseline sample")
+    p.add_argument("--sample", type=int, default=131072, help="cells in the cpu_baseline sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-variants", action="store_true")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="first run a plain 512 MiB device copy (known HBM traffic) for counter calibration")
+    p.add_argument("--no-precision", action="store_true")
+    p.add_argument("--counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                   help="summarise two rocprofv3 --pmc folders instead of benchmarking")
     return p.parse_args()
 
 
@@ -142,8 +237,73 @@ def bench_blocks(args, R, W, torch, dev):
     print(json.dumps(res), flush=True)
 
 
+def precision_report(R, torch, dev, W, dt, sample=16384):
+    """Storage-precision experiment: FP32 and bfloat16 residual storage of 64^3
+    tables on the spherical workload.  Errors of the GPU outputs on a seeded
+    sample against the oracle's FP64 tables (rates and the Newton step), and
+    the Newton throughput over the whole workload with each storage form."""
+    from oracle import step as S
+    from oracle import tables as T
+    cells = W.workload(2)
+    n = cells["n_e"].size
+    idx = np.sort(np.random.default_rng(W.SEED_BASE + 2).choice(n, size=sample, replace=False))
+    sub = [cells[f][idx] for f in W.FIELDS]
+    spec = T.TableSpec.default(64)
+    ts = S.TableSet(spec, T.build_tables(spec))
+    ref = S.table_rates(ts, *sub)
+    ref.update({k: v for k, v in S.step_be(ts, *sub, dt).items() if k in ("T_e_new", "T_i_new")})
+    full = {k: torch.from_numpy(np.ascontiguousarray(cells[k])).to(dev) for k in W.FIELDS}
+    part = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in zip(W.FIELDS, sub)}
+    rep = {"workload": "spherical-polar profile 128^3 (%d cells); errors on a %d-cell seeded sample vs the "
+                       "oracle's FP64 64^3 tables" % (n, sample)}
+    for vd in ("f32", "bf16"):
+        gt = R.Tables.build(R.default_spec(64, vd))
+        o = R.cool_step(gt, part, dt, diagnostics=True)
+        errs = {}
+        for g, rk in (("Q_rad", "q_rad"), ("Q_cc", "q_cc"), ("Q_brem", "q_brem"), ("Q_syn", "q_syn"),
+                      ("eta", "eta"), ("T_e_new", "T_e_new"), ("T_i_new", "T_i_new")):
+            e = np.abs(o[g].cpu().numpy() - ref[rk]) / np.maximum(np.abs(ref[rk]), 1e-300)
+            errs[g] = {"max": float(e.max()), "median": float(np.median(e))}
+        out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")}
+        out["status"] = torch.empty(n, dtype=torch.uint8, device=dev)
+        ms, _ = time_steps(R, torch, gt, full, dt, R.default_opts(), out, 10, 2)
+        rep[vd] = {"table_bytes": (8 if vd == "bf16" else 16) * 64 ** 3 + (2 if vd == "bf16" else 4) * 64 ** 3,
+                   "newton_ms": ms, "Gcell_per_s": n / (ms * 1e-3) / 1e9, "rel_err": errs}
+    return rep
+
+
+def accuracy_report(R, torch, dev):
+    """Model accuracy of the two time integrators over one step: backward Euler
+    (Newton) and 16 explicit substeps on the GPU with 64^3 tables, against the
+    stored tight-tolerance ODE solution of 256 seeded cells (tests/golden)."""
+    path = os.path.join(ROOT, "tests", "golden", "ode_reference_iid2m_256.json")
+    with open(path) as fh:
+        d = json.load(fh)
+    cols = np.array(d["cells"], dtype=np.float64)
+    state = {f: torch.from_numpy(np.ascontiguousarray(cols[:, k])).to(dev) for k, f in enumerate(d["fields"])}
+    te_ode = np.array(d["T_e_ode"])
+    change = np.abs(te_ode - cols[:, 1]) / cols[:, 1]
+    gt = R.Tables.build(R.default_spec(64))
+    rep = {"reference": d["description"]}
+    bands = ((0.0, 1e-4), (1e-4, 1e-2), (1e-2, 0.3), (0.3, np.inf))
+    for scheme in ("newton", "explicit16"):
+        o = R.cool_step(gt, state, d["dt"], R.default_opts(scheme=scheme))
+        e = np.abs(o["T_e_new"].cpu().numpy() - te_ode) / te_ode
+        by = {}
+        for lo, hi in bands:
+            m = (change >= lo) & (change < hi)
+            if m.any():
+                by["|dT_e/T_e| in [%g, %g)" % (lo, hi)] = {"cells": int(m.sum()), "median": float(np.median(e[m])),
+                                                         "max": float(e[m].max())}
+        rep[scheme] = {"T_e_rel_err_median": float(np.median(e)), "T_e_rel_err_max": float(e.max()),
+                       "by_change": by}
+    return rep
+
+
 def main():
     args = parse()
+    if args.counters:
+        return counters_summary(*args.counters)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the cooling step shards trivially by cells; see the design notes)", file=sys.stderr)
@@ -198,13 +358,15 @@ def main():
         "config": {"workload": desc, "cells": n, "scheme": args.scheme, "variant": args.variant,
                    "table_n": table_n, "dt_s": dt, "T_floor_K": opts.T_floor},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if (args.workload == "iid256" and table_n == 128 and
+                                                       args.scheme == "newton" and args.variant == "auto") else None},
         "table_build_s": t_build,
         "status_counts": {str(int(v)): int(c) for v, c in zip(*np.unique(status, return_counts=True))},
     }
     if not args.no_variants:
         var = {}
-        for name, kw, steps in (("newton_uncompacted", dict(block=256), 3),
+        for name, kw, steps in (("newton_plain", dict(block=256), 3),
                                 ("rates_global", dict(scheme="rates"), 5),
                                 ("explicit16_global", dict(scheme="explicit16"), 3),
                                 ("rates_direct", dict(scheme="rates", variant="direct"), 1)):
@@ -214,6 +376,11 @@ def main():
                 var[name] = {"ms": vms, "Gcell_per_s": n / (vms * 1e-3) / 1e9}
             except R.RadcoolError as e:
                 var[name] = {"error": str(e)}
+        # the same step reading bfloat16-stored tables (half the table bytes)
+        t16 = R.Tables.build(R.default_spec(table_n, "bf16"))
+        vms, _ = time_steps(R, torch, t16, state, dt, opts, out, 3, 1)
+        var["newton_bf16_tables"] = {"ms": vms, "Gcell_per_s": n / (vms * 1e-3) / 1e9}
+        t16.destroy()
         # differentiation form: adjoint of the Newton step (cotangents of the
         # radiated energy) with table-entry gradients
         R.cool_step(tables, state, dt, opts, out=out)
@@ -238,6 +405,9 @@ def main():
         # the timed configuration again, so that the outputs below are its own
         R.cool_step(tables, state, dt, opts, out=out)
         torch.cuda.synchronize()
+    if not args.no_precision:
+        res["precision"] = precision_report(R, torch, dev, W, dt)
+        res["accuracy"] = accuracy_report(R, torch, dev)
     if not args.no_cpu_baseline:
         gpu_out = {k: out[k].cpu().numpy() for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")}
         rng = np.random.default_rng(20250513)

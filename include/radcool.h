@@ -68,7 +68,8 @@ enum {
   RC_ST_CLAMP_COOL = 2,  /* a cooling-table coordinate of the input state was out of range (clamped) */
   RC_ST_CLAMP_COUL = 4,  /* a Coulomb-table coordinate of the input state was out of range (clamped) */
   RC_ST_FLOOR = 8,       /* the implicit update ended on the temperature floor */
-  RC_ST_MAXITER = 16     /* the solver hit max_iter; outputs are the best bracketed iterate */
+  RC_ST_MAXITER = 16,    /* the solver hit max_iter; outputs are the best bracketed iterate */
+  RC_ST_GAS_FLOOR = 32   /* radiative cooling off for the step: input T_e + T_i below T_floor_gas */
 };
 
 /* One table's three axes, log10-spaced: node k of axis a is
@@ -79,21 +80,35 @@ typedef struct {
   double hi[3];
 } rc_axes;
 
+/* Storage precision of the table residuals (the values minus their
+ * least-squares affine part in node-index space, which is kept in FP64). */
+enum { RC_VALUE_F32 = 0, RC_VALUE_BF16 = 1 };
+
 typedef struct {
   rc_axes cool;          /* log10 N [cm^-2], log10 T_e [K], log10 B [G] */
   rc_axes coul;          /* log10 n_e [cm^-3], log10 T_e [K], log10 T_i [K] */
   double ln_lambda;      /* Coulomb logarithm, Sec. II.G (default 20) */
+  int32_t value_dtype;   /* RC_VALUE_F32 (default) or RC_VALUE_BF16: the residual
+                            rounded once more, to nearest-even bfloat16 (storage
+                            experiment: half the table bytes, 2^-9 relative
+                            rounding of the residual) */
+  int32_t reserved;      /* must be 0 */
 } rc_table_spec;
 
 typedef struct rc_tables_s* rc_tables;   /* opaque, library-owned device tables */
 
-/* Per-cell input state: device pointers, FP64, length n. */
+/* Per-cell input state: device pointers, FP64, length n.  T_floor_gas is
+ * optional (NULL = none): a per-cell floor on the gas temperature T_e + T_i
+ * [K] (Sec. III.B.2, e.g. from rc_disk_inputs); a cell whose input gas
+ * temperature lies below it has zero radiative cooling for the step (Coulomb
+ * exchange still acts) and status bit RC_ST_GAS_FLOOR. */
 typedef struct {
   const double* n_e;
   const double* T_e;
   const double* T_i;
   const double* B;
   const double* H;
+  const double* T_floor_gas;
 } rc_state;
 
 /* Per-cell outputs: device pointers, length n; NULL = not written.
@@ -112,13 +127,24 @@ typedef struct {
 } rc_out;
 
 enum { RC_SCHEME_NEWTON = 0, RC_SCHEME_EXPLICIT16 = 1, RC_SCHEME_RATES = 2 };
+
+/* How the tables are read.  GLOBAL (what AUTO selects) gathers the corners
+ * with plain global loads, through the vector L1 and L2 caches.  LDS is not
+ * available in this build (RC_EUNSUPPORTED).  TEX names the texture-memory path
+ * of the paper's GPU (Sec. III.A); gfx950 exposes no texture sampling to HIP,
+ * so it returns RC_EUNSUPPORTED.  DIRECT evaluates the closed forms of
+ * Sec. II per cell instead of tables (rates scheme only). */
 enum { RC_VARIANT_AUTO = 0, RC_VARIANT_GLOBAL = 1, RC_VARIANT_LDS = 2, RC_VARIANT_TEX = 3, RC_VARIANT_DIRECT = 4 };
 
 typedef struct {
   int32_t scheme;        /* RC_SCHEME_*: backward Euler (Newton), 16-substep explicit, or rates only */
   int32_t variant;       /* RC_VARIANT_*: how tables are read; DIRECT evaluates closed forms (no tables) */
   int32_t max_iter;      /* Newton iteration cap (default 60) */
-  int32_t block;         /* threads per workgroup, 0 = library choice */
+  int32_t block;         /* 0 = library choice: for the Newton scheme a sequence of
+                            launches that set slow cells aside and finish them on
+                            dense wavefronts (per-call scratch from a library-owned
+                            stream-ordered pool); 64, 128, 192 or 256 = one
+                            launch, one cell per thread, with that workgroup size */
   double T_floor;        /* K, cooling is zero below it (Sec. III.B.2; default 1e6) */
   double tol;            /* target relative accuracy of T_e' (default 1e-12): a Newton step
                             below sqrt(tol) in ln T_e' ends the solve */
@@ -137,7 +163,7 @@ rc_status rc_default_opts(rc_step_opts* opts);
 /* Build the four tables on the current device from the closed forms of Sec. II
  * (node values in FP64 on the GPU; a least-squares affine function of the node
  * indices is removed from each log2 table on the host and the residual is
- * stored in FP32).  Synchronous.  *out receives a new handle owned by the
+ * stored in FP32, or in bfloat16 when spec->value_dtype says so).  Synchronous.  *out receives a new handle owned by the
  * caller (release with rc_tables_destroy). */
 rc_status rc_build_tables(const rc_table_spec* spec, void* stream, rc_tables* out);
 
@@ -145,8 +171,10 @@ rc_status rc_build_tables(const rc_table_spec* spec, void* stream, rc_tables* ou
  * residuals of the four tables back to back, each C-ordered [i0][i1][i2] over
  * its axes (three cooling tables of n0*n1*n2 values, then the Coulomb table),
  * and coeffs holds 4 x 4 FP64 affine coefficients (c0, c1, c2, c3 per table,
- * value = c0 + c1 i0 + c2 i1 + c3 i2 + resid).  Synchronous; host buffers are
- * only read during the call. */
+ * value = c0 + c1 i0 + c2 i1 + c3 i2 + resid).  For RC_VALUE_BF16 the
+ * residuals are rounded to bfloat16 (nearest, ties to even) on import, and
+ * export returns the rounded values.  Synchronous; host buffers are only read
+ * during the call. */
 rc_status rc_tables_import(const rc_table_spec* spec, const float* resid, const double* coeffs,
                            void* stream, rc_tables* out);
 
@@ -258,6 +286,41 @@ rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, int64_t n, d
                                 const rc_step_opts* opts, const rc_fwd* fwd, const rc_cotangent* cot,
                                 const rc_grad* grad, void* stream);
 
+/* Disk parameters of the upstream inputs (Sec. II.F, III.B.2). */
+typedef struct {
+  double gamma;          /* adiabatic index (the paper's runs: 5/3) */
+  double spin;           /* dimensionless black-hole spin a, |a| <= 1 (the paper: 0.9375) */
+  double h_floor;        /* target thickness (H/R)_floor of the temperature floor (the paper: 0.1) */
+  double r_g;            /* gravitational radius G M / c^2 [cm] */
+} rc_disk_params;
+
+/* Per-cell inputs upstream of the step, from GRMHD primitives (device
+ * pointers, FP64, length n): rest-mass density rho [g cm^-3], gas pressure P
+ * and internal energy density u = rho eps [erg cm^-3], radius r [r_g].
+ * Writes (either may be NULL):
+ *   H_th        = c_s / Omega_K [cm], c_s^2 = gamma P / (rho c^2 + u + P),
+ *                 Omega_K = 1 / (r^(3/2) + a) in c / r_g   (Sec. II.F, eq. H_thermal);
+ *   T_floor_gas = (pi/2) (h_floor Omega_K r)^2 m_p c^2 / k_B [K], the floor on the
+ *                 gas temperature T_e + T_i (Sec. III.B.2; P / rho = k (T_e + T_i) / m_p),
+ *                 ready for rc_state.T_floor_gas.
+ * Cells with a non-finite input, rho < 0, u < 0, P <= 0 or r <= 0 get NaN.
+ * RC_EINVAL for NULL inputs, n < 0, gamma <= 1, |spin| > 1, h_floor < 0 or
+ * r_g <= 0.  Asynchronous on stream. */
+rc_status rc_disk_inputs(const double* rho, const double* P, const double* u, const double* r, int64_t n,
+                         const rc_disk_params* params, double* H_th, double* T_floor_gas, void* stream);
+
+/* Radiation-pressure temperature correction (Sec. IV, eq. total_pressure),
+ * a post-processing step: where tau_sca = n_e sigma_T H > tau_crit (the paper:
+ * 4.6, fewer than 1 % of photons escaping unscattered) the pressure
+ * n_e k (T_e + T_i) is shared between radiation and gas with T_i held, and
+ * T_e_out solves a T^4 + n_e k T = n_e k T_e (a = 4 sigma_SB / c; unique root,
+ * T_e_out < T_e); elsewhere T_e_out = T_e.  Device pointers, FP64, length n;
+ * thick (uint8, may be NULL) flags the corrected cells.  Cells with a
+ * non-finite or non-positive input get NaN and thick = 0.  Asynchronous on
+ * stream. */
+rc_status rc_rad_pressure_correction(const double* n_e, const double* T_e, const double* H, int64_t n,
+                                     double tau_crit, double* T_e_out, uint8_t* thick, void* stream);
+
 /* The physical constants compiled into the library, in this order:
  * c, k_B, h, m_e, m_p, e, sigma_T, sigma_SB; returns how many were written
  * (at most n). */
@@ -273,7 +336,9 @@ rc_status rc_selftest_node_host(const rc_table_spec* spec, int32_t table, int32_
 /* Host-side self-test of special functions (same source as the device code):
  * which = 0,1,2: exponentially scaled K_nu(x) for nu = which;
  * which = 3: the synchrotron tail integral J(x) = int_x^inf s I'(s) ds;
- * which = 4: x_c solving ln(I'(x)/x) = x (input is the log right side).
+ * which = 4: x_c solving ln(I'(x)/x) = x (input is the log right side);
+ * which = 5..9: the solver's own elementary functions ln x, log10 x,
+ * ln(1 + x), e^x, 2^x (finite arguments; positive for the logarithms).
  * For tests only. */
 rc_status rc_selftest_special_host(int32_t which, const double* x, double* y, int64_t n);
 
@@ -282,9 +347,16 @@ rc_status rc_selftest_special_host(int32_t which, const double* x, double* y, in
  * host arrays of length n.  For tests only. */
 rc_status rc_selftest_step_host(const rc_table_spec* spec, const float* resid, const double* coeffs,
                                 const double* n_e, const double* T_e, const double* T_i,
-                                const double* B, const double* H, int64_t n, double dt,
+                                const double* B, const double* H, const double* T_floor_gas, int64_t n, double dt,
                                 const rc_step_opts* opts, double* T_e_new, double* T_i_new,
                                 double* Q_rad, double* Q_cc, uint8_t* status);
+
+/* Host-side self-tests of rc_disk_inputs and rc_rad_pressure_correction: the
+ * same per-cell source on host arrays.  For tests only. */
+rc_status rc_selftest_disk_host(const double* rho, const double* P, const double* u, const double* r, int64_t n,
+                                const rc_disk_params* params, double* H_th, double* T_floor_gas);
+rc_status rc_selftest_radp_host(const double* n_e, const double* T_e, const double* H, int64_t n, double tau_crit,
+                                double* T_e_out, uint8_t* thick);
 
 /* Host-side self-test of the per-cell adjoint (same source as the GPU
  * kernel) on tables in storage form (host memory).  Arrays of length n; cot_*

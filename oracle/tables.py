@@ -137,10 +137,20 @@ def affine_eval(coeffs, i0, i1, i2):
     return coeffs[0] + coeffs[1] * i0 + coeffs[2] * i1 + coeffs[3] * i2
 
 
-def quantize(y):
-    """FP32 storage form of one table: (coeffs FP64[4], residual FP32, stored FP64 values).
+def round_bf16(a):
+    """Round float32 values to bfloat16 (the upper 16 bits of a binary32),
+    round to nearest, ties to even; returned as float32.  Finite inputs."""
+    bits = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (bits >> 16) & 1
+    bits = (bits + 0x7FFF + lsb) & 0xFFFF0000
+    return bits.astype(np.uint32).view(np.float32)
 
-    The stored table is affine(i) + float64(float32(y - affine(i))).  Multilinear
+
+def quantize(y, value_dtype="f32"):
+    """Storage form of one table: (coeffs FP64[4], residual FP32, stored FP64 values).
+
+    The stored table is affine(i) + float64(r) with r = float32(y - affine(i)),
+    and for the bfloat16 form r additionally rounded to bfloat16.  Multilinear
     interpolation reproduces the affine part exactly, so only the residual is
     rounded; its magnitude is what sets the storage error.
     """
@@ -148,14 +158,18 @@ def quantize(y):
     grids = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in y.shape], indexing="ij")
     base = affine_eval(coeffs, *grids)
     resid = (y - base).astype(np.float32)
+    if value_dtype == "bf16":
+        resid = round_bf16(resid)
+    elif value_dtype != "f32":
+        raise ValueError("value_dtype must be 'f32' or 'bf16'")
     return coeffs, resid, base + resid.astype(np.float64)
 
 
-def quantize_tables(tables):
+def quantize_tables(tables, value_dtype="f32"):
     """Apply ``quantize`` to every table; returns (coeffs dict, resid dict, stored dict)."""
     co, re, st = {}, {}, {}
     for k in TABLE_NAMES:
-        co[k], re[k], st[k] = quantize(tables[k])
+        co[k], re[k], st[k] = quantize(tables[k], value_dtype)
     return co, re, st
 
 

@@ -18,6 +18,7 @@ namespace rc {
 
 struct BwdArgs {
   const double *n_e, *T_e, *T_i, *B, *H;
+  const double* T_floor_gas;   // optional per-cell gas-temperature floor
   const double *x, *z;
   const uint8_t* status;
   const double *g_x, *g_z, *g_qr, *g_qc;
@@ -56,7 +57,8 @@ __global__ __launch_bounds__(256) void k_backward(Tab tab, StepParams P, BwdArgs
   const double x = a.newton ? a.x[i] : a.T_e[i];
   const double z = a.newton ? a.z[i] : a.T_i[i];
   const uint8_t st = a.status ? a.status[i] : (uint8_t)0;
-  cell_vjp(tab, P, a.c1, a.c2, a.k1, a.k2, a.n_e[i], a.T_e[i], a.T_i[i], a.B[i], a.H[i], x, z, st,
+  cell_vjp(tab, P, a.c1, a.c2, a.k1, a.k2, a.n_e[i], a.T_e[i], a.T_i[i], a.B[i], a.H[i],
+           a.T_floor_gas ? a.T_floor_gas[i] : 0.0, x, z, st,
            a.g_x ? a.g_x[i] : 0.0, a.g_z ? a.g_z[i] : 0.0, a.g_qr ? a.g_qr[i] : 0.0, a.g_qc ? a.g_qc[i] : 0.0,
            a.newton != 0, a.o_tab != nullptr, &g, sc);
   if (a.o_n) a.o_n[i] = g.n_e;
@@ -107,6 +109,7 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
     return set_error(RC_ESTATE, "rc_cool_step_backward: tables live on another device than the current one");
   BwdArgs a;
   a.n_e = state->n_e; a.T_e = state->T_e; a.T_i = state->T_i; a.B = state->B; a.H = state->H;
+  a.T_floor_gas = state->T_floor_gas;
   a.x = fwd ? fwd->T_e_new : nullptr;
   a.z = fwd ? fwd->T_i_new : nullptr;
   a.status = fwd ? fwd->status : nullptr;
@@ -133,8 +136,10 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
     a.g_se = (double*)t->d_gscratch;
     hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, hs, a.g_se, a.vc);
   }
-  GlobalTab tab{t->d_cool, t->d_coul, t->spec.cool.n[1], t->spec.cool.n[2], t->spec.coul.n[1], t->spec.coul.n[2]};
-  hipLaunchKernelGGL(k_backward<GlobalTab>, dim3((unsigned)grid), dim3(block), 0, hs, tab, P, a, n);
+  with_tab(t, [&](auto tab) {
+    hipLaunchKernelGGL(k_backward<decltype(tab)>, dim3((unsigned)grid), dim3(block), 0, hs, tab, P, a, n);
+    return 0;
+  });
   if (a.o_tab) hipLaunchKernelGGL(k_finish_se, dim3(1024), dim3(256), 0, hs, a.o_tab, a.g_se, a.vc);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "rc_cool_step_backward launch");
@@ -163,9 +168,11 @@ extern "C" rc_status rc_selftest_backward_host(const rc_table_spec* spec, const 
   if (opts->scheme == RC_SCHEME_EXPLICIT16) return set_error(RC_EUNSUPPORTED, "explicit scheme has no adjoint");
   if (newton && (!T_e_new || !T_i_new || !status)) return set_error(RC_EINVAL, "forward outputs required");
   const long vc = (long)volume(spec->cool);
+  const std::vector<float> stored = storage_values(*spec, resid);
   std::vector<float4> cool((size_t)vc);
-  for (long i = 0; i < vc; ++i) cool[i] = make_float4(resid[i], resid[vc + i], resid[2 * vc + i], 0.0f);
-  GlobalTab tab{cool.data(), resid + 3 * vc, spec->cool.n[1], spec->cool.n[2], spec->coul.n[1], spec->coul.n[2]};
+  for (long i = 0; i < vc; ++i) cool[i] = make_float4(stored[i], stored[vc + i], stored[2 * vc + i], 0.0f);
+  GlobalTab tab{cool.data(), stored.data() + 3 * vc, spec->cool.n[1], spec->cool.n[2], spec->coul.n[1],
+                spec->coul.n[2]};
   struct HostScatter {
     double* g;
     long vc;
@@ -183,7 +190,7 @@ extern "C" rc_status rc_selftest_backward_host(const rc_table_spec* spec, const 
   for (int64_t i = 0; i < n; ++i) {
     CellGrad g;
     cell_vjp(tab, P, spec->cool.n[1], spec->cool.n[2], spec->coul.n[1], spec->coul.n[2], n_e[i], T_e[i], T_i[i],
-             B[i], H[i], newton ? T_e_new[i] : T_e[i], newton ? T_i_new[i] : T_i[i], status ? status[i] : 0,
+             B[i], H[i], 0.0, newton ? T_e_new[i] : T_e[i], newton ? T_i_new[i] : T_i[i], status ? status[i] : 0,
              cot_T_e_new ? cot_T_e_new[i] : 0.0, cot_T_i_new ? cot_T_i_new[i] : 0.0,
              cot_Q_rad ? cot_Q_rad[i] : 0.0, cot_Q_cc ? cot_Q_cc[i] : 0.0, newton, g_tables != nullptr, &g, sc);
     if (g_n_e) g_n_e[i] = g.n_e;

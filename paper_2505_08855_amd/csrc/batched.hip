@@ -11,7 +11,6 @@
 
 #include "radcool.h"
 #include "rc_internal.hpp"
-#include "rc_compact.hpp"
 #include "rc_kernels.hpp"
 
 namespace rc {
@@ -54,33 +53,8 @@ __global__ __launch_bounds__(256) void k_batched(Tab tab, StepParams P, StateArg
     for (int k = threadIdx.x; k < blk.n_cells; k += blockDim.x) {
       const int64_t i = blk.first_cell + k;
       CellOut r;
-      cool_cell<SCHEME>(tab, P, dt, s.n_e[i], s.T_e[i], s.T_i[i], s.B[i], s.H[i], diag, &r);
+      cool_cell<SCHEME>(tab, P, dt, s.n_e[i], s.T_e[i], s.T_i[i], s.B[i], s.H[i], floor_gas_at(s, i), diag, &r);
       store(o, i, r);
-    }
-  }
-}
-
-// Newton scheme with in-workgroup compaction: each work item's cells are
-// processed in tiles of kTile (the workgroup size is fixed to kTile).
-template <class Tab>
-__global__ __launch_bounds__(kTile) void k_batched_compact(Tab tab, StepParams P, StateArgs s, OutArgs o, BatchArgs b) {
-  __shared__ ParkedTile L;
-  __shared__ int item;
-  const bool diag = o.Q_brem || o.Q_syn || o.eta;
-  for (;;) {
-    if (threadIdx.x == 0) item = (int)atomicAdd(b.counter, 1u);
-    __syncthreads();
-    const int w = item;
-    __syncthreads();
-    if (w >= b.n_blocks) break;
-    const rc_block blk = b.blocks[w];
-    if (blk.first_cell < 0 || blk.n_cells <= 0 || blk.first_cell > b.n_total - blk.n_cells || blk.state_id < 0 ||
-        blk.state_id >= b.n_states)
-      continue;
-    const double dt = b.dt[blk.state_id];
-    for (int k0 = 0; k0 < blk.n_cells; k0 += kTile) {
-      const int count = blk.n_cells - k0 < kTile ? blk.n_cells - k0 : kTile;
-      newton_tile(tab, P, dt, blk.first_cell + k0, count, s, o, diag, L);
     }
   }
 }
@@ -123,17 +97,19 @@ rc_status fill_scratch(void* scratch, const double* dts, int n_states, hipStream
   return e == hipSuccess ? RC_OK : hip_fail(e, "batched: copying dt_per_state");
 }
 
-hipError_t launch_batched(int scheme, const GlobalTab& tab, const StepParams& P, const StateArgs& s, const OutArgs& o,
-                          const BatchArgs& b, int block, int grid, hipStream_t hs) {
+hipError_t launch_batched(int scheme, const rc_tables_s* t, const StepParams& P, const StateArgs& s,
+                          const OutArgs& o, const BatchArgs& b, int block, int grid, hipStream_t hs) {
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, hs, b.counter);
-  if (scheme == RC_SCHEME_NEWTON && block == kTile)
-    hipLaunchKernelGGL(k_batched_compact<GlobalTab>, dim3(grid), dim3(kTile), 0, hs, tab, P, s, o, b);
-  else if (scheme == RC_SCHEME_NEWTON)
-    hipLaunchKernelGGL((k_batched<SCHEME_NEWTON, GlobalTab>), dim3(grid), dim3(block), 0, hs, tab, P, s, o, b);
-  else if (scheme == RC_SCHEME_EXPLICIT16)
-    hipLaunchKernelGGL((k_batched<SCHEME_EXPLICIT16, GlobalTab>), dim3(grid), dim3(block), 0, hs, tab, P, s, o, b);
-  else
-    hipLaunchKernelGGL((k_batched<SCHEME_RATES, GlobalTab>), dim3(grid), dim3(block), 0, hs, tab, P, s, o, b);
+  with_tab(t, [&](auto tab) {
+    using Tab = decltype(tab);
+    if (scheme == RC_SCHEME_NEWTON)
+      hipLaunchKernelGGL((k_batched<SCHEME_NEWTON, Tab>), dim3(grid), dim3(block), 0, hs, tab, P, s, o, b);
+    else if (scheme == RC_SCHEME_EXPLICIT16)
+      hipLaunchKernelGGL((k_batched<SCHEME_EXPLICIT16, Tab>), dim3(grid), dim3(block), 0, hs, tab, P, s, o, b);
+    else
+      hipLaunchKernelGGL((k_batched<SCHEME_RATES, Tab>), dim3(grid), dim3(block), 0, hs, tab, P, s, o, b);
+    return 0;
+  });
   return hipGetLastError();
 }
 
@@ -180,12 +156,11 @@ extern "C" rc_status rc_cool_step_batched(rc_tables t, const rc_state* state, in
   }
   st = fill_scratch(t->d_counter, dt_per_state, n_states, (hipStream_t)stream, &b);
   if (st != RC_OK) return st;
-  StateArgs s{state->n_e, state->T_e, state->T_i, state->B, state->H};
+  StateArgs s{state->n_e, state->T_e, state->T_i, state->B, state->H, state->T_floor_gas};
   OutArgs o{out->T_e_new, out->T_i_new, out->Q_rad, out->Q_cc, out->Q_brem, out->Q_syn, out->eta, out->status};
-  GlobalTab tab{t->d_cool, t->d_coul, t->spec.cool.n[1], t->spec.cool.n[2], t->spec.coul.n[1], t->spec.coul.n[2]};
   const int block = opts->block ? opts->block : 256;
   const int grid = compute_units() * 4;
-  const hipError_t e = launch_batched(opts->scheme, tab, P, s, o, b, block, grid, (hipStream_t)stream);
+  const hipError_t e = launch_batched(opts->scheme, t, P, s, o, b, block, grid, (hipStream_t)stream);
   return e == hipSuccess ? RC_OK : hip_fail(e, "rc_cool_step_batched launch");
 }
 
@@ -213,7 +188,7 @@ extern "C" rc_status rc_plan_create(rc_tables t, const rc_state* state, int64_t 
   if (!p) return set_error(RC_ENOMEM, "rc_plan_create: host allocation failed");
   p->t = t;
   p->P = P;
-  p->s = StateArgs{state->n_e, state->T_e, state->T_i, state->B, state->H};
+  p->s = StateArgs{state->n_e, state->T_e, state->T_i, state->B, state->H, state->T_floor_gas};
   p->o = OutArgs{out->T_e_new, out->T_i_new, out->Q_rad, out->Q_cc, out->Q_brem, out->Q_syn, out->eta, out->status};
   p->b = b;
   p->scheme = opts->scheme;
@@ -222,7 +197,6 @@ extern "C" rc_status rc_plan_create(rc_tables t, const rc_state* state, int64_t 
   st = fill_scratch(p->counter, dt_per_state, n_states, hs, &p->b);
   if (st == RC_OK && hipStreamSynchronize(hs) != hipSuccess) st = set_error(RC_EDEVICE, "rc_plan_create: copying dt");
   if (st != RC_OK) { (void)hipFree(p->counter); delete p; return st; }
-  GlobalTab tab{t->d_cool, t->d_coul, t->spec.cool.n[1], t->spec.cool.n[2], t->spec.coul.n[1], t->spec.coul.n[2]};
   const int cus = compute_units();
   p->block = opts->block ? opts->block : 256;
   p->grid = cus * 4;
@@ -236,9 +210,9 @@ extern "C" rc_status rc_plan_create(rc_tables t, const rc_state* state, int64_t 
     for (int bi = 0; bi < 3; ++bi) {
       for (int gi = 0; gi < 4; ++gi) {
         const int blk = blocks_c[bi], grid = cus * per_cu[gi];
-        e = launch_batched(p->scheme, tab, p->P, p->s, p->o, p->b, blk, grid, hs);   // warm-up
+        e = launch_batched(p->scheme, t, p->P, p->s, p->o, p->b, blk, grid, hs);   // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, hs);
-        if (e == hipSuccess) e = launch_batched(p->scheme, tab, p->P, p->s, p->o, p->b, blk, grid, hs);
+        if (e == hipSuccess) e = launch_batched(p->scheme, t, p->P, p->s, p->o, p->b, blk, grid, hs);
         if (e == hipSuccess) e = hipEventRecord(e1, hs);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.0f;
@@ -262,7 +236,7 @@ extern "C" rc_status rc_plan_create(rc_tables t, const rc_state* state, int64_t 
   e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    const hipError_t le = launch_batched(p->scheme, tab, p->P, p->s, p->o, p->b, p->block, p->grid, cap);
+    const hipError_t le = launch_batched(p->scheme, t, p->P, p->s, p->o, p->b, p->block, p->grid, cap);
     e = hipStreamEndCapture(cap, &p->graph);
     if (le != hipSuccess) e = le;
   }

@@ -41,7 +41,8 @@ bool axes_ok(const rc_axes& a) {
 }
 
 bool spec_ok(const rc_table_spec* s) {
-  return s && axes_ok(s->cool) && axes_ok(s->coul) && std::isfinite(s->ln_lambda) && s->ln_lambda > 0.0;
+  return s && axes_ok(s->cool) && axes_ok(s->coul) && std::isfinite(s->ln_lambda) && s->ln_lambda > 0.0 &&
+         (s->value_dtype == RC_VALUE_F32 || s->value_dtype == RC_VALUE_BF16) && s->reserved == 0;
 }
 
 int64_t volume(const rc_axes& a) { return (int64_t)a.n[0] * a.n[1] * a.n[2]; }
@@ -76,6 +77,8 @@ extern "C" rc_status rc_default_spec(rc_table_spec* spec, int32_t n) {
     spec->coul.n[k] = n; spec->coul.lo[k] = kl[k]; spec->coul.hi[k] = kh[k];
   }
   spec->ln_lambda = 20.0;
+  spec->value_dtype = RC_VALUE_F32;
+  spec->reserved = 0;
   return RC_OK;
 }
 
@@ -131,23 +134,65 @@ void affine_fit(const double* y, const int n[3], double co[4]) {
   }
 }
 
+// float -> bfloat16 bits, round to nearest, ties to even (finite values)
+uint16_t bf16_bits(float v) {
+  uint32_t b;
+  std::memcpy(&b, &v, 4);
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+
+float bf16_round(float v) {
+  const uint32_t b = (uint32_t)bf16_bits(v) << 16;
+  float r;
+  std::memcpy(&r, &b, 4);
+  return r;
+}
+
+// the residuals as stored: rounded to bfloat16 for that storage form
+void round_storage(rc_tables_s* t) {
+  if (t->spec.value_dtype != RC_VALUE_BF16) return;
+  for (float& v : t->resid) v = bf16_round(v);
+}
+
+std::vector<float> storage_values(const rc_table_spec& s, const float* resid) {
+  const size_t n = (size_t)(3 * volume(s.cool) + volume(s.coul));
+  std::vector<float> v(resid, resid + n);
+  if (s.value_dtype == RC_VALUE_BF16)
+    for (float& x : v) x = bf16_round(x);
+  return v;
+}
+
 rc_status upload(rc_tables_s* t, void* stream) {
   const int64_t vc = volume(t->spec.cool), vk = volume(t->spec.coul);
-  std::vector<float> packed((size_t)vc * 4);
-  for (int64_t i = 0; i < vc; ++i) {
-    packed[4 * i + 0] = t->resid[i];
-    packed[4 * i + 1] = t->resid[vc + i];
-    packed[4 * i + 2] = t->resid[2 * vc + i];
-    packed[4 * i + 3] = 0.0f;
+  const bool bf = t->spec.value_dtype == RC_VALUE_BF16;
+  const size_t cool_bytes = (bf ? 8 : 16) * (size_t)vc, coul_bytes = (bf ? 2 : 4) * (size_t)vk;
+  std::vector<float> packed;
+  std::vector<uint16_t> packed16;
+  try {
+    if (bf) packed16.resize(4 * (size_t)vc + (size_t)vk);
+    else packed.resize(4 * (size_t)vc);
+  } catch (...) {
+    return fail(RC_ENOMEM, "host allocation of the packed tables failed");
   }
-  hipError_t e = hipMalloc(&t->d_cool, sizeof(float4) * vc);
+  for (int64_t i = 0; i < vc; ++i) {
+    const float v[4] = {t->resid[i], t->resid[vc + i], t->resid[2 * vc + i], 0.0f};
+    for (int k = 0; k < 4; ++k) {
+      if (bf) packed16[4 * i + k] = bf16_bits(v[k]);
+      else packed[4 * i + k] = v[k];
+    }
+  }
+  if (bf)
+    for (int64_t i = 0; i < vk; ++i) packed16[4 * vc + i] = bf16_bits(t->resid[3 * vc + i]);
+  hipError_t e = hipMalloc(&t->d_cool, cool_bytes);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(cooling tables)");
-  e = hipMalloc(&t->d_coul, sizeof(float) * vk);
+  e = hipMalloc(&t->d_coul, coul_bytes);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(Coulomb table)");
   hipStream_t s = (hipStream_t)stream;
-  e = hipMemcpyAsync(t->d_cool, packed.data(), sizeof(float4) * vc, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(t->d_coul, t->resid.data() + 3 * vc, sizeof(float) * vk, hipMemcpyHostToDevice, s);
+  const void* hc = bf ? (const void*)packed16.data() : (const void*)packed.data();
+  const void* hk = bf ? (const void*)(packed16.data() + 4 * vc) : (const void*)(t->resid.data() + 3 * vc);
+  e = hipMemcpyAsync(t->d_cool, hc, cool_bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(t->d_coul, hk, coul_bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "table upload");
   return RC_OK;
@@ -155,7 +200,6 @@ rc_status upload(rc_tables_s* t, void* stream) {
 
 void destroy_tables(rc_tables_s* t) {
   if (!t) return;
-  release_textures(t);
   if (t->d_cool) (void)hipFree(t->d_cool);
   if (t->d_coul) (void)hipFree(t->d_coul);
   if (t->d_counter) (void)hipFree(t->d_counter);
@@ -235,6 +279,7 @@ rc_status finish_from_values(rc_tables_s* t, const std::vector<double>& y, void*
           dst[idx] = (float)(src[idx] - base);
         }
   }
+  round_storage(t);
   return upload(t, stream);
 }
 
@@ -296,6 +341,7 @@ extern "C" rc_status rc_tables_import(const rc_table_spec* spec, const float* re
       if (!std::isfinite(coeffs[4 * k + j])) { destroy_tables(t); return fail(RC_EINVAL, "rc_tables_import: non-finite coefficient"); }
       t->coef[k][j] = coeffs[4 * k + j];
     }
+  round_storage(t);
   st = upload(t, stream);
   if (st != RC_OK) { destroy_tables(t); return st; }
   *out = t;
@@ -329,7 +375,7 @@ extern "C" rc_status rc_tables_destroy(rc_tables t) {
 
 namespace {
 
-constexpr char kFileMagic[8] = {'R', 'C', 'T', 'A', 'B', 'L', 'E', '1'};
+constexpr char kFileMagic[8] = {'R', 'C', 'T', 'A', 'B', 'L', 'E', '2'};
 
 // FNV-1a, 64 bit, over the payload bytes
 uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
@@ -417,7 +463,7 @@ extern "C" rc_status rc_selftest_node_host(const rc_table_spec* spec, int32_t ta
 }
 
 extern "C" rc_status rc_selftest_special_host(int32_t which, const double* x, double* y, int64_t n) {
-  if (!x || !y || n < 0 || which < 0 || which > 4) return fail(RC_EINVAL, "rc_selftest_special_host: bad argument");
+  if (!x || !y || n < 0 || which < 0 || which > 9) return fail(RC_EINVAL, "rc_selftest_special_host: bad argument");
   for (int64_t i = 0; i < n; ++i) {
     double k0, k1, k2;
     switch (which) {
@@ -426,7 +472,12 @@ extern "C" rc_status rc_selftest_special_host(int32_t which, const double* x, do
         y[i] = which == 0 ? k0 : (which == 1 ? k1 : k2);
         break;
       case 3: y[i] = exp(ln_tail(x[i])); break;
-      default: y[i] = solve_xc(x[i]); break;
+      case 4: y[i] = solve_xc(x[i]); break;
+      case 5: y[i] = flog(x[i]); break;
+      case 6: y[i] = flog10(x[i]); break;
+      case 7: y[i] = flog1p(x[i]); break;
+      case 8: y[i] = fexp(x[i]); break;
+      default: y[i] = fexp2(x[i]); break;
     }
   }
   return RC_OK;
@@ -434,7 +485,8 @@ extern "C" rc_status rc_selftest_special_host(int32_t which, const double* x, do
 
 extern "C" rc_status rc_selftest_step_host(const rc_table_spec* spec, const float* resid, const double* coeffs,
                                            const double* n_e, const double* T_e, const double* T_i,
-                                           const double* B, const double* H, int64_t n, double dt,
+                                           const double* B, const double* H, const double* T_floor_gas, int64_t n,
+                                           double dt,
                                            const rc_step_opts* opts, double* T_e_new, double* T_i_new,
                                            double* Q_rad, double* Q_cc, uint8_t* status) {
   if (!spec_ok(spec) || !resid || !coeffs) return fail(RC_EINVAL, "rc_selftest_step_host: bad table arguments");
@@ -448,15 +500,17 @@ extern "C" rc_status rc_selftest_step_host(const rc_table_spec* spec, const floa
   rc_status st = make_params(&host, dt, opts, &P);
   if (st != RC_OK) return st;
   const int64_t vc = volume(spec->cool);
+  const std::vector<float> stored = storage_values(*spec, resid);
   std::vector<float4> cool((size_t)vc);
-  for (int64_t i = 0; i < vc; ++i) cool[i] = make_float4(resid[i], resid[vc + i], resid[2 * vc + i], 0.0f);
-  GlobalTab tab{cool.data(), resid + 3 * vc, spec->cool.n[1], spec->cool.n[2], spec->coul.n[1], spec->coul.n[2]};
+  for (int64_t i = 0; i < vc; ++i) cool[i] = make_float4(stored[i], stored[vc + i], stored[2 * vc + i], 0.0f);
+  GlobalTab tab{cool.data(), stored.data() + 3 * vc, spec->cool.n[1], spec->cool.n[2], spec->coul.n[1],
+                spec->coul.n[2]};
   for (int64_t i = 0; i < n; ++i) {
     CellOut o;
     if (opts->variant == RC_VARIANT_DIRECT) {
-      direct_rates(P, n_e[i], T_e[i], T_i[i], B[i], H[i], &o);
+      direct_rates(P, n_e[i], T_e[i], T_i[i], B[i], H[i], T_floor_gas ? T_floor_gas[i] : 0.0, &o);
     } else {
-      cool_cell_any(tab, P, n_e[i], T_e[i], T_i[i], B[i], H[i], false, &o);
+      cool_cell_any(tab, P, n_e[i], T_e[i], T_i[i], B[i], H[i], T_floor_gas ? T_floor_gas[i] : 0.0, false, &o);
     }
     if (T_e_new) T_e_new[i] = o.T_e_new;
     if (T_i_new) T_i_new[i] = o.T_i_new;

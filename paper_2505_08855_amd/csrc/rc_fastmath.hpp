@@ -1,0 +1,112 @@
+// Elementary functions for the per-cell solver (FP64, host and device).
+//
+// The general-purpose library versions handle every special case (NaN, inf,
+// zero, negative arguments, extra-precise intermediate steps) and cost about
+// 100 VALU instructions per logarithm on gfx950.  The solver only takes
+// logarithms of finite positive values and exponentials of finite moderate
+// ones, so these versions use textbook reductions and short polynomials:
+//
+//   log:  x = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(f),
+//         f = (m - 1) / (m + 1), |f| <= 0.1716, summed as the atanh series
+//         f + f^3/3 + ... + f^21/21 (first omitted term below 2^-56 relative);
+//         e ln 2 with ln 2 split into a 21-bit head (exact products) and tail.
+//   exp2: y = k + f with k = rint(y), |f| <= 1/2; 2^f by its Taylor series in
+//         f (coefficients (ln 2)^j / j!, j <= 13; first omitted term < 2^-57).
+//   exp:  s = k ln 2 + r (Cody-Waite: k ln2_head exact), |r| <= 0.347,
+//         e^r by its Taylor series to r^13 / 13!.
+//   log1p: u = 1 + v, log1p(v) = ln(u) v / (u - 1) (Goldberg's correction
+//         for the rounding of 1 + v; exact when u == 1).
+//
+// Accuracy is a few ulp over the whole double range; the library's host
+// self-test compares every function with the C library.
+#pragma once
+
+#include "rc_physics.hpp"
+
+namespace rc {
+
+constexpr double kLn2Hi = 0x1.62e42p-1;             // ln 2 rounded to 21 bits
+constexpr double kLn2Lo = 0x1.fdf473de6af28p-22;    // ln 2 - kLn2Hi
+constexpr double kLog2E = 0x1.71547652b82fep+0;     // 1 / ln 2
+constexpr double kInvLn10 = 0x1.bcb7b1526e50ep-2;   // 1 / ln 10
+constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;  // sqrt(1/2)
+
+// ln x for finite x > 0
+RC_HD double flog(double x) {
+  int e;
+  double m = frexp(x, &e);           // [1/2, 1)
+  if (m < kSqrtHalf) {
+    m += m;
+    --e;
+  }
+  const double f = (m - 1.0) / (m + 1.0);   // m - 1 is exact
+  const double s = f * f;
+  double p = 1.0 / 21.0;
+  p = fma(p, s, 1.0 / 19.0);
+  p = fma(p, s, 1.0 / 17.0);
+  p = fma(p, s, 1.0 / 15.0);
+  p = fma(p, s, 1.0 / 13.0);
+  p = fma(p, s, 1.0 / 11.0);
+  p = fma(p, s, 1.0 / 9.0);
+  p = fma(p, s, 1.0 / 7.0);
+  p = fma(p, s, 1.0 / 5.0);
+  p = fma(p, s, 1.0 / 3.0);
+  const double f2 = f + f;
+  const double lm = fma(f2 * s, p, f2);    // 2 atanh f
+  const double de = (double)e;
+  return fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
+}
+
+RC_HD double flog10(double x) { return flog(x) * kInvLn10; }
+
+// ln(1 + v) for finite v > -1
+RC_HD double flog1p(double v) {
+  const double u = 1.0 + v;
+  if (u == 1.0) return v;
+  return flog(u) * (v / (u - 1.0));
+}
+
+// 2^y for finite y
+RC_HD double fexp2(double y) {
+  const double k = rint(y);
+  const double f = y - k;             // exact
+  double p = 0x1.816193166d0f9p-40;   // (ln 2)^13 / 13!
+  p = fma(p, f, 0x1.c3bd650fc2986p-36);
+  p = fma(p, f, 0x1.e8cac7351bb25p-32);
+  p = fma(p, f, 0x1.e4cf5158b8ecap-28);
+  p = fma(p, f, 0x1.b5253d395e7c4p-24);
+  p = fma(p, f, 0x1.62c0223a5c824p-20);
+  p = fma(p, f, 0x1.ffcbfc588b0c7p-17);
+  p = fma(p, f, 0x1.430912f86c787p-13);
+  p = fma(p, f, 0x1.5d87fe78a6731p-10);
+  p = fma(p, f, 0x1.3b2ab6fba4e77p-7);
+  p = fma(p, f, 0x1.c6b08d704a0c0p-5);
+  p = fma(p, f, 0x1.ebfbdff82c58fp-3);
+  p = fma(p, f, 0x1.62e42fefa39efp-1);
+  p = fma(p, f, 1.0);
+  return ldexp(p, (int)k);
+}
+
+// e^s; arguments outside |s| < 700 (including inf and NaN) take the library path
+RC_HD double fexp(double s) {
+  if (!(fabs(s) < 700.0)) return exp(s);
+  const double k = rint(s * kLog2E);
+  const double r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, s));
+  double p = 1.0 / 6227020800.0;      // 1 / 13!
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)k);
+}
+
+}  // namespace rc

@@ -113,8 +113,8 @@ struct QradPartials {
 RC_HD QradPartials qrad_partials(const CoolPoint& cp, double n_e, double x, double B, double H, bool on) {
   QradPartials r = {0, 0, 0, 0, 0, 0, 0};
   if (!on) return r;
-  const double vb = exp2(cp.yb) / (H * H);
-  const double vse = exp2(cp.yse) / H;
+  const double vb = fexp2(cp.yb) / (H * H);
+  const double vse = fexp2(cp.yse) / H;
   const double qt = vb + vse;
   double du[3];
   for (int a = 0; a < 3; ++a) du[a] = kLn2 * (vb * cp.dyb[a] + vse * cp.dyse[a]);
@@ -156,15 +156,17 @@ struct CellGrad {
 // fall in the same table cell their corner contributions are merged first.
 template <class Tab, class Scatter>
 RC_HD void cell_vjp(const Tab& tab, const StepParams& P, int c1, int c2, int k1, int k2, double n_e, double T_e,
-                    double T_i, double B, double H, double x, double z, unsigned char status, double g_x,
-                    double g_z, double g_qr, double g_qc, bool newton, bool want_tables, CellGrad* out,
+                    double T_i, double B, double H, double floor_gas, double x, double z, unsigned char status,
+                    double g_x, double g_z, double g_qr, double g_qc, bool newton, bool want_tables, CellGrad* out,
                     Scatter& sc) {
+  // radiative cooling switched off for the step by the gas-temperature floor
+  const bool cool_off = T_e + T_i < floor_gas;
   out->n_e = out->T_e = out->T_i = out->B = out->H = 0.0;
   if (status & ST_INVALID) return;
   const double dt = P.dt;
   const double c = kUperNKT * n_e * kKB;
   const double c_n = kUperNKT * kKB;
-  const double lne = log10(n_e), lH = log10(H), lB = log10(B);
+  const double lne = flog10(n_e), lH = flog10(H), lB = flog10(B);
   double gn = 0.0, gTe = 0.0, gTi = 0.0, gB = 0.0, gH = 0.0;
   // corner coefficients of the two evaluation points (solution, input)
   double cb[2] = {0.0, 0.0}, cse[2] = {0.0, 0.0}, cc[2] = {0.0, 0.0};
@@ -173,12 +175,12 @@ RC_HD void cell_vjp(const Tab& tab, const StepParams& P, int c1, int c2, int k1,
   bool have[2] = {false, false};
   if (newton) {
     const bool floor = (status & ST_FLOOR) != 0;
-    const double lx = log10(x), lz = log10(z);
+    const double lx = flog10(x), lz = flog10(z);
     cp[0] = cool_point(tab, P, lne + lH, lx, lB, c1, c2);
     kp[0] = coul_point(tab, P, lne, lx, lz, k1, k2);
     have[0] = true;
-    const QradPartials qp = qrad_partials(cp[0], n_e, x, B, H, x >= P.T_floor);
-    const double kc = exp2(kp[0].y);
+    const QradPartials qp = qrad_partials(cp[0], n_e, x, B, H, !cool_off && x >= P.T_floor);
+    const double kc = fexp2(kp[0].y);
     const double kn = kLn2 * kc * kp[0].dy[0] / (n_e * kLn10);
     const double kx = kLn2 * kc * kp[0].dy[1] / (x * kLn10);
     const double kz = kLn2 * kc * kp[0].dy[2] / (z * kLn10);
@@ -209,12 +211,12 @@ RC_HD void cell_vjp(const Tab& tab, const StepParams& P, int c1, int c2, int k1,
     gTi = g_z;
   }
   if (g_qr != 0.0 || g_qc != 0.0) {
-    const double lte = log10(T_e), lti = log10(T_i);
+    const double lte = flog10(T_e), lti = flog10(T_i);
     cp[1] = cool_point(tab, P, lne + lH, lte, lB, c1, c2);
     kp[1] = coul_point(tab, P, lne, lte, lti, k1, k2);
     have[1] = true;
-    const QradPartials qp = qrad_partials(cp[1], n_e, T_e, B, H, T_e >= P.T_floor);
-    const double kc = exp2(kp[1].y);
+    const QradPartials qp = qrad_partials(cp[1], n_e, T_e, B, H, !cool_off && T_e >= P.T_floor);
+    const double kc = fexp2(kp[1].y);
     const double kn = kLn2 * kc * kp[1].dy[0] / (n_e * kLn10);
     const double kx = kLn2 * kc * kp[1].dy[1] / (T_e * kLn10);
     const double kz = kLn2 * kc * kp[1].dy[2] / (T_i * kLn10);

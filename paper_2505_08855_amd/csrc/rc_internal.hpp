@@ -21,12 +21,10 @@ struct rc_tables_s {
   rc_table_spec spec{};
   double coef[4][4] = {};
   std::vector<float> resid;         // host copy of the storage form, [brem][synch][eta][coul]
-  float4* d_cool = nullptr;         // interleaved {brem, synch, eta, 0} per cooling node
-  float* d_coul = nullptr;          // planar Coulomb residuals
-  // texture objects for the sampling variant (created on first use)
-  hipArray_t tex_arr[4] = {nullptr, nullptr, nullptr, nullptr};
-  hipTextureObject_t tex[4] = {0, 0, 0, 0};
-  bool tex_ready = false;
+  // device storage: FP32 form float4 {brem, synch, eta, 0} per cooling node and
+  // float per Coulomb node; bfloat16 form uint2 (4 x bf16) and uint16
+  void* d_cool = nullptr;
+  void* d_coul = nullptr;
   void* d_counter = nullptr;        // work-queue counter of the batched kernel (allocated on first use)
   void* d_gscratch = nullptr;       // backward: synch * eta table-gradient accumulator (first use)
 };
@@ -40,6 +38,18 @@ bool spec_ok(const rc_table_spec* s);
 int64_t volume(const rc_axes& a);
 void fill_axes(const rc_table_spec& s, AxisP ax[6]);
 rc_status make_params(rc_tables t, double dt, const rc_step_opts* o, StepParams* P);
-void release_textures(rc_tables_s* t);
+// host copy of residuals in their storage form (bfloat16-rounded for that form)
+std::vector<float> storage_values(const rc_table_spec& s, const float* resid);
+
+// Call f with the table accessor of t's storage form (GlobalTab or GlobalTabBF16).
+template <class F>
+auto with_tab(const rc_tables_s* t, F&& f) {
+  const rc_table_spec& s = t->spec;
+  if (s.value_dtype == RC_VALUE_BF16)
+    return f(GlobalTabBF16{(const uint2*)t->d_cool, (const unsigned short*)t->d_coul, s.cool.n[1], s.cool.n[2],
+                           s.coul.n[1], s.coul.n[2]});
+  return f(GlobalTab{(const float4*)t->d_cool, (const float*)t->d_coul, s.cool.n[1], s.cool.n[2], s.coul.n[1],
+                     s.coul.n[2]});
+}
 
 }  // namespace rc

@@ -15,7 +15,10 @@ struct StateArgs {
   const double* T_i;
   const double* B;
   const double* H;
+  const double* T_floor_gas;   // optional per-cell gas-temperature floor (NULL = none)
 };
+
+__device__ inline double floor_gas_at(const StateArgs& s, int64_t i) { return s.T_floor_gas ? s.T_floor_gas[i] : 0.0; }
 
 struct OutArgs {
   double* T_e_new;

@@ -17,8 +17,11 @@
 //   driven to zero by Newton in s = ln x on
 //     G(s) = log1p([c (x - T_e) + c (z - T_i) + dt Q_rad(x)] / (c (T_e + T_i))),
 //   whose slope uses dz/dx = -(dE2/dx)/(dE2/dz) (the off-diagonal Jacobian
-//   blocks).  Every derivative is the exact derivative of the interpolant
-//   inside the current table cell.  The iteration starts at x = T_e, moves in
+//   blocks).  On cooling iterates away from x = T_e the step is instead
+//   Newton's on the log-log form ln(dt Q_rad) - ln(c (T_e - x) + c (T_i - z)),
+//   which has the same sign and converges faster for strong cooling.  Every
+//   derivative is the exact derivative of the interpolant inside the current
+//   table cell.  The iteration starts at x = T_e, moves in
 //   the direction the source points and keeps a sign bracket, so it lands on
 //   the first root met from the initial state; when the step would cross the
 //   temperature floor it probes G at the floor and projects onto it if the
@@ -34,13 +37,20 @@
 // iterate leaves the cached cell.
 #pragma once
 
+#include "rc_fastmath.hpp"
 #include "rc_physics.hpp"
 
 namespace rc {
 
 enum : unsigned char {
-  ST_INVALID = 1, ST_CLAMP_COOL = 2, ST_CLAMP_COUL = 4, ST_FLOOR = 8, ST_MAXITER = 16
+  ST_INVALID = 1, ST_CLAMP_COOL = 2, ST_CLAMP_COUL = 4, ST_FLOOR = 8, ST_MAXITER = 16, ST_GAS_FLOOR = 32
 };
+
+// Electron floor of a cell whose cooling is switched off for the step (its
+// input gas temperature lies below the gas-temperature floor): above every
+// temperature, so Q_rad is zero along the whole solve.
+constexpr double kNoCoolingFloor = 1e300;
+constexpr double kLnNoCoolingFloor = 690.7755278982137;    // ln 1e300
 enum { SCHEME_NEWTON = 0, SCHEME_EXPLICIT16 = 1, SCHEME_RATES = 2 };
 
 struct AxisP {
@@ -54,6 +64,7 @@ struct StepParams {
   AxisP ax[6];          // cooling (N, T_e, B), Coulomb (n_e, T_e, T_i)
   double coef[4][4];    // affine part of each log2 table in node-index space
   double dt, T_floor, tol, ln_lambda;
+  double ln_T_floor, sqrt_tol;   // log(T_floor), sqrt(tol)
   int max_iter, scheme;
 };
 
@@ -90,6 +101,25 @@ struct GlobalTab {
   RC_HD float coul_at(int i0, int i1, int i2) const { return coul[((long)i0 * k1 + i1) * k2 + i2]; }
 };
 
+// bfloat16 bits -> float (exact: bfloat16 is the upper half of a binary32)
+RC_HD float bf16_to_float(unsigned v) { return __builtin_bit_cast(float, v << 16); }
+
+// The same tables stored as bfloat16 residuals (storage-precision
+// experiment): 8 bytes per cooling node {brem, synch, eta, 0}, 2 bytes per
+// Coulomb node.  Widened to float on load; the arithmetic after that is the
+// FP32-storage path's.
+struct GlobalTabBF16 {
+  const uint2* cool;
+  const unsigned short* coul;
+  int c1, c2;
+  int k1, k2;
+  RC_HD float4 cool_at(int i0, int i1, int i2) const {
+    const uint2 p = cool[((long)i0 * c1 + i1) * c2 + i2];
+    return make_float4(bf16_to_float(p.x & 0xffffu), bf16_to_float(p.x >> 16), bf16_to_float(p.y & 0xffffu), 0.0f);
+  }
+  RC_HD float coul_at(int i0, int i1, int i2) const { return bf16_to_float(coul[((long)i0 * k1 + i1) * k2 + i2]); }
+};
+
 struct CellOut {
   double T_e_new, T_i_new, q_rad, q_cc, q_brem, q_syn, eta;
   unsigned char status;
@@ -120,12 +150,20 @@ struct CellSolver {
   int ie, ii;
   double K0, v00, v10, v01, v11;
   unsigned char clamp;
+  bool cool_off;        // radiative cooling switched off for this cell (gas-temperature floor)
 
   RC_HD CellSolver(const Tab& t, const StepParams& p) : tab(t), P(p) {}
 
-  // per-cell constants and fixed coordinates; returns s0 = ln T_e
-  RC_HD double setup(double n_e, double te, double ti, double b, double h, double dt_) {
+  // electron temperature floor of this cell and its logarithm
+  RC_HD double Tf() const { return cool_off ? kNoCoolingFloor : P.T_floor; }
+  RC_HD double lnTf() const { return cool_off ? kLnNoCoolingFloor : P.ln_T_floor; }
+
+  // per-cell constants and fixed coordinates; returns s0 = ln T_e.  A cell
+  // whose gas temperature T_e + T_i lies below floor_gas (0 = none) has no
+  // radiative cooling this step.
+  RC_HD double setup(double n_e, double te, double ti, double b, double h, double dt_, double floor_gas = 0.0) {
     dt = dt_;
+    cool_off = te + ti < floor_gas;
     T_e = te;
     T_i = ti;
     H = h;
@@ -134,18 +172,18 @@ struct CellSolver {
     tau_sca = 2.0 * n_e * kSigmaT * h;
     invH = 1.0 / h;
     invH2 = invH * invH;
-    const double lne = log10(n_e);
-    const Coord cN = axis_coord(lne + log10(h), P.ax[0]);
-    const Coord cB = axis_coord(log10(b), P.ax[2]);
+    const double lne = flog10(n_e);
+    const Coord cN = axis_coord(lne + flog10(h), P.ax[0]);
+    const Coord cB = axis_coord(flog10(b), P.ax[2]);
     const Coord cn = axis_coord(lne, P.ax[3]);
     iN = cN.i; tN = cN.t;
     iB = cB.i; tB = cB.t;
     in_ = cn.i; tn = cn.t;
-    const double s0 = log(te);
+    const double s0 = flog(te);
     const double lte = s0 * (1.0 / kLn10);
-    clamp = 0;
+    clamp = cool_off ? ST_GAS_FLOOR : 0;
     if (cN.clamped || cB.clamped || axis_coord(lte, P.ax[1]).clamped) clamp |= ST_CLAMP_COOL;
-    if (cn.clamped || axis_coord(lte, P.ax[4]).clamped || axis_coord(log10(ti), P.ax[5]).clamped)
+    if (cn.clamped || axis_coord(lte, P.ax[4]).clamped || axis_coord(flog10(ti), P.ax[5]).clamped)
       clamp |= ST_CLAMP_COUL;
     iT = ie = ii = -1;
     return s0;
@@ -192,15 +230,28 @@ struct CellSolver {
     K0 = co[0] + co[1] * (in_ + tn) + co[2] * (double)je + co[3] * (double)ji;
   }
 
-  // bridged Q_rad at T = x (lx = log10 x; zero when cooling is off) and dQ_rad/dln x
-  RC_HD void q_rad(double x, double lx, bool on, double* q, double* dq) {
+  // Corner gathers of one evaluation at T_e = x (cooling coordinate cT,
+  // Coulomb coordinate ce) and T_i = z (coordinate ci).  When either cached
+  // cell no longer contains the point both tables are re-read in one block,
+  // so that all their loads are in flight together and a re-gather costs one
+  // memory latency, not two; the table whose cell did not change re-reads
+  // lines that are already cached.  With the default axes the two T_e axes
+  // coincide and both cells change together anyway.
+  RC_HD void gather(const Coord& cT, const Coord& ce, const Coord& ci, bool cool_needed) {
+    if ((cool_needed && cT.i != iT) || ce.i != ie || ci.i != ii) {
+      load_cool(cT.i);
+      load_coul(ce.i, ci.i);
+    }
+  }
+
+  // bridged Q_rad at T = x (cooling coordinate cT, its cell gathered; zero
+  // when cooling is off) and dQ_rad/dln x
+  RC_HD void q_rad(double x, const Coord& cT, bool on, double* q, double* dq) {
     if (!on) { *q = 0.0; *dq = 0.0; return; }
-    const Coord cT = axis_coord(lx, P.ax[1]);
-    if (cT.i != iT) load_cool(cT.i);
     const double t = cT.t;
     const double g = cT.dfdu * (1.0 / kLn10);       // d t / d ln x
-    const double vb = exp2(Ab + Sb * t) * invH2;
-    const double vs = exp2(Ase + Sse * t) * invH;
+    const double vb = fexp2(Ab + Sb * t) * invH2;
+    const double vs = fexp2(Ase + Sse * t) * invH;
     const double qthin = vb + vs;
     const double dlq = kLn2 * g * (vb * Sb + vs * Sse) / qthin;
     const double x2 = x * x;
@@ -211,11 +262,9 @@ struct CellSolver {
     *dq = *q * (dlq - dD / D);
   }
 
-  // Coulomb coefficient v_c at (T_e coordinate ce, T_i = z) and the partial
-  // derivatives d ln v_c / d ln T_e, d ln v_c / d ln T_i
-  RC_HD double kcoul(const Coord& ce, double z, double* dlx, double* dlz) {
-    const Coord ci = axis_coord(log10(z), P.ax[5]);
-    if (ce.i != ie || ci.i != ii) load_coul(ce.i, ci.i);
+  // Coulomb coefficient v_c at (T_e coordinate ce, T_i coordinate ci, cell
+  // gathered) and the partial derivatives d ln v_c / d ln T_e, d ln v_c / d ln T_i
+  RC_HD double kcoul_at(const Coord& ce, const Coord& ci, double* dlx, double* dlz) const {
     const double te = ce.t, ti = ci.t;
     const double c2 = P.coef[3][2], c3 = P.coef[3][3];
     const double y = K0 + c2 * te + c3 * ti + (1.0 - te) * (1.0 - ti) * v00 + te * (1.0 - ti) * v10 +
@@ -224,26 +273,34 @@ struct CellSolver {
     const double dyi = c3 + (1.0 - te) * (v01 - v00) + te * (v11 - v10);
     *dlx = kLn2 * dye * ce.dfdu * (1.0 / kLn10);
     *dlz = kLn2 * dyi * ci.dfdu * (1.0 / kLn10);
-    return exp2(y);
+    return fexp2(y);
+  }
+
+  // the same at T_i = z, gathering the Coulomb cell if z left the cached one
+  RC_HD double kcoul(const Coord& ce, double z, double* dlx, double* dlz) {
+    const Coord ci = axis_coord(flog10(z), P.ax[5]);
+    if (ce.i != ie || ci.i != ii) load_coul(ce.i, ci.i);
+    return kcoul_at(ce, ci, dlx, dlz);
   }
 
   // z(x) solving E2 = c (z - T_i) + dt (z - x) v_c(x, z) = 0 inside
   // [min(x, T_i), max(x, T_i)], where E2 changes sign; returns z and dz/dx.
-  // *K_first receives v_c at the first trial z (the warm start).
-  RC_HD double solve_z(double x, const Coord& ce, double zg, double* dzdx, double* K_first) {
+  // z0 is the first trial z, already inside that interval, with its Coulomb
+  // coordinate ci0 (cell gathered); *K_first receives v_c there.
+  RC_HD double solve_z(double x, const Coord& ce, double z0, const Coord& ci0, double* dzdx, double* K_first) {
     double lo = fmin(x, T_i), hi = fmax(x, T_i);
-    double z = fmin(fmax(zg, lo), hi);
+    double z = z0;
     double K = 0.0, dlx = 0.0, dlz = 0.0;
     if (!(hi > lo)) {
       // x == T_i: z = T_i solves E2; implicit derivative dz/dx = dt K / (c + dt K)
-      K = kcoul(ce, z, &dlx, &dlz);
+      K = kcoul_at(ce, ci0, &dlx, &dlz);
       if (K_first) *K_first = K;
       *dzdx = dt * K / (c + dt * K);
       return lo;
     }
     double dEz = c;
     for (int it = 0; it < 60; ++it) {
-      K = kcoul(ce, z, &dlx, &dlz);
+      K = it == 0 ? kcoul_at(ce, ci0, &dlx, &dlz) : kcoul(ce, z, &dlx, &dlz);
       if (it == 0 && K_first) *K_first = K;
       const double E = c * (z - T_i) + dt * (z - x) * K;
       dEz = c + dt * K + dt * (z - x) * K * dlz / z;
@@ -264,25 +321,49 @@ struct CellSolver {
     return z;
   }
 
-  // outer residual G = log1p([c (x - T_e) + c (z - T_i) + dt Q_rad(x)] / (c (T_e + T_i)))
-  // at x = exp(s), its slope dG/ds, and (optionally) Q_rad(x) and v_c at the warm start
-  RC_HD double outer(double s, double x, bool on, double* z, double* dG, double* q_out, double* K_first) {
+  // Outer residual G = log1p([c (x - T_e) + c (z - T_i) + dt Q_rad(x)] / (c (T_e + T_i)))
+  // at x = exp(s), with its slope dG/ds, Q_rad(x), v_c at the warm start and
+  // dz/dx.  With want3, *ds3 receives the Newton step of the log-log form
+  //   G3 = ln(dt Q_rad(x)) - ln R,   R = c (T_e - x) + c (T_i - z),
+  // which has the sign of G wherever R > 0, provided that form is well
+  // conditioned here: |d ln R / ds| = c x (1 + dz/dx) / R <= 2 (near x = T_e,
+  // R -> 0 and G3 is strongly curved).  Otherwise *ds3 is NaN.  Why: in a
+  // strongly cooling cell near its root numer / cS is small, so G follows
+  // dt Q_rad(x), a steep convex function of s, and Newton on G creeps down
+  // from above; ln Q_rad is close to linear in s, so Newton on G3 converges
+  // quadratically from much further away.
+  RC_HD double outer(double s, double x, bool on, bool want3, double* z, double* dG, double* q_out,
+                     double* K_first, double* dzdx_out, double* ds3) {
     const double lx = s * (1.0 / kLn10);
     double q, dq, dzdx;
-    q_rad(x, lx, on, &q, &dq);
+    const Coord cT = axis_coord(lx, P.ax[1]);
     const Coord ce = axis_coord(lx, P.ax[4]);
-    *z = solve_z(x, ce, *z, &dzdx, K_first);
+    const double z0 = fmin(fmax(*z, fmin(x, T_i)), fmax(x, T_i));
+    const Coord ci = axis_coord(flog10(z0), P.ax[5]);
+    gather(cT, ce, ci, on);
+    q_rad(x, cT, on, &q, &dq);
+    *z = solve_z(x, ce, z0, ci, &dzdx, K_first);
     const double numer = c * ((x - T_e) + (*z - T_i)) + dt * q;
-    *dG = (c * x * (1.0 + dzdx) + dt * dq) / (cS + numer);
-    if (q_out) *q_out = q;
-    return log1p(numer / cS);
+    const double cx = c * x * (1.0 + dzdx);
+    *dG = (cx + dt * dq) / (cS + numer);
+    *q_out = q;
+    *dzdx_out = dzdx;
+    *ds3 = __builtin_nan("");
+    if (want3) {
+      const double R = c * ((T_e - x) + (T_i - *z));
+      if (q > 0.0 && R > 0.0 && cx <= 2.0 * R) {
+        const double dG3 = dq / q + cx / R;
+        if (dG3 > 0.0) *ds3 = -flog(dt * q / R) / dG3;
+      }
+    }
+    return flog1p(numer / cS);
   }
 
   // Newton driver.  Every evaluation of the outer residual goes through one
   // call site (newton_round: evaluate at the pending point, then choose the
   // next one), so the inlined rate code exists once in the kernel; the whole
-  // iteration state lives in NewtonState so that a kernel can also park a cell
-  // between rounds (in-workgroup compaction).
+  // iteration state lives in NewtonState so that a kernel can also set a cell
+  // aside between rounds and resume it in a later launch (straggler deferral).
   enum { FIRST = 0, ITER = 1, PROBE_ON = 2, PROBE_OFF = 3, FINAL = 4 };
   enum { F_LO_KNOWN = 1, F_FLOOR_PENDING = 2, F_HEATING = 4, F_ON = 8 };
 
@@ -292,27 +373,34 @@ struct CellSolver {
     ns.z_floor = T_i;
     ns.kind = FIRST; ns.iters = 0;
     ns.se = s0; ns.xe = T_e;
-    ns.flags = (T_e >= P.T_floor) ? F_ON : 0;
+    ns.flags = (T_e >= Tf()) ? F_ON : 0;
   }
 
   // one evaluation at the pending point; returns true when the cell is done
   // (T_e_new, T_i_new and the FLOOR / MAXITER bits are then in o)
   RC_HD bool newton_round(NewtonState& ns, CellOut* o) {
-    const double T_floor = P.T_floor;
-    const double sf = log(T_floor);
+    const double T_floor = Tf();
+    const double sf = lnTf();
     const double tol = P.tol;
-    double ze = ns.z, dGe, q, Kf;
-    const double Ge = outer(ns.se, ns.xe, (ns.flags & F_ON) != 0, &ze, &dGe, &q, &Kf);
+    for (;;) {   // one evaluation, plus the z-only one of a cell that converges in it
     const int kind = ns.kind;
-    bool propose = false;
+    // the log-log step only serves cooling iterates
+    const bool want3 = kind == ITER && !(ns.flags & F_HEATING) && (ns.flags & F_ON);
+    double ze = ns.z, dGe, q, Kf, dzdx_e, ds3;
+    const double Ge = outer(ns.se, ns.xe, (ns.flags & F_ON) != 0, want3, &ze, &dGe, &q, &Kf, &dzdx_e, &ds3);
     if (kind == FINAL) {
       o->T_e_new = ns.xe;
       o->T_i_new = ze;
       return true;
-    } else if (kind == FIRST) {
+    }
+    bool propose = false;
+    // dz/dx at the iterate when this round's evaluation became the iterate;
+    // 0 otherwise (the next inner solve then starts from z unchanged)
+    double dzdx = 0.0;
+    if (kind == FIRST) {
       o->q_rad = q;
       o->q_cc = (T_i - T_e) * Kf;
-      ns.G = Ge; ns.dG = dGe; ns.z = ze;
+      ns.G = Ge; ns.dG = dGe; ns.z = ze; dzdx = dzdx_e;
       if (ns.G == 0.0) { o->T_e_new = T_e; o->T_i_new = ze; return true; }
       const bool on0 = (ns.flags & F_ON) != 0;
       if (ns.G > 0.0) {
@@ -336,7 +424,7 @@ struct CellSolver {
       ns.z_floor = ze;
       if (Ge < 0.0) {                          // root above the floor
         ns.lo = sf; ns.flags |= F_LO_KNOWN;
-        ns.s = sf; ns.G = Ge; ns.dG = dGe; ns.z = ze;
+        ns.s = sf; ns.G = Ge; ns.dG = dGe; ns.z = ze; dzdx = dzdx_e;
         propose = true;
       } else if (!(ns.flags & F_HEATING) && T_i < T_floor) {
         // the root can also lie under the floor, where cooling is off
@@ -355,14 +443,14 @@ struct CellSolver {
         }
       } else if (Ge > 0.0) {                   // descent continues under the floor
         ns.hi = sf; ns.lo = log(T_i); ns.flags |= F_LO_KNOWN;
-        ns.s = sf; ns.G = Ge; ns.dG = dGe; ns.z = ze;
+        ns.s = sf; ns.G = Ge; ns.dG = dGe; ns.z = ze; dzdx = dzdx_e;
         propose = true;
       } else {
         o->T_e_new = T_floor; o->T_i_new = ns.z_floor; o->status |= ST_FLOOR;
         return true;
       }
     } else {  // ITER
-      ns.s = ns.se; ns.G = Ge; ns.dG = dGe; ns.z = ze;
+      ns.s = ns.se; ns.G = Ge; ns.dG = dGe; ns.z = ze; dzdx = dzdx_e;
       if (ns.G > 0.0) ns.hi = ns.s;
       else if (ns.G < 0.0) { ns.lo = ns.s; ns.flags |= F_LO_KNOWN; }
       if (ns.G == 0.0 || ((ns.flags & F_LO_KNOWN) && (ns.hi - ns.lo) <= tol)) {
@@ -376,19 +464,25 @@ struct CellSolver {
       }
       propose = true;
     }
-    if (propose) {
+    if (!propose) return false;
+    {
       const double s = ns.s, lo = ns.lo, hi = ns.hi;
       const bool lo_known = (ns.flags & F_LO_KNOWN) != 0;
       const bool floor_pending = (ns.flags & F_FLOOR_PENDING) != 0;
-      double sn = s - ns.G / ns.dG;
-      const bool newton_ok = (ns.dG > 0.0) && (sn == sn);
-      if (newton_ok && fabs(sn - s) <= sqrt(tol) && !(floor_pending && sn < sf)) {
+      const bool use3 = (ds3 == ds3) && ns.G > 0.0;   // ds3 is only set on a cooling ITER
+      double sn = use3 ? s + ds3 : s - ns.G / ns.dG;
+      const bool newton_ok = (use3 || ns.dG > 0.0) && (sn == sn);
+      if (newton_ok && fabs(sn - s) <= P.sqrt_tol && !(floor_pending && sn < sf)) {
         // converged: Newton converges quadratically, so once the step is
         // below sqrt(tol) the error left after taking it is O(tol); only
-        // z(x) remains to be solved at the new point.  Tested before the
-        // bracket safeguard, which could reject a step below an end's ulp.
-        ns.kind = FINAL; ns.se = sn; ns.xe = exp(sn); ns.flags &= ~F_ON;
-        return false;
+        // z(x) remains, solved at the new point (cooling off, so that only
+        // the inner solve runs) in this same round, from the first-order
+        // warm start z + dz/dx (x' - x).  Tested before the bracket
+        // safeguard, which could reject a step below an end's ulp.
+        const double xn = fexp(sn);
+        ns.z += dzdx * (xn - ns.xe);
+        ns.kind = FINAL; ns.se = sn; ns.xe = xn; ns.flags &= ~F_ON;
+        continue;
       }
       if (floor_pending && (!newton_ok || sn < sf)) {
         // the descent would cross the floor (decided on the raw Newton step:
@@ -400,10 +494,13 @@ struct CellSolver {
       if (!newton_ok || sn >= hi || (lo_known ? sn <= lo : sn < lo)) {
         sn = lo_known ? 0.5 * (lo + hi) : 0.5 * (lo + s);
       }
-      ns.kind = ITER; ns.se = sn; ns.xe = exp(sn);
+      const double xn = fexp(sn);
+      ns.z += dzdx * (xn - ns.xe);             // first-order warm start of the next inner solve
+      ns.kind = ITER; ns.se = sn; ns.xe = xn;
       if (ns.xe >= T_floor) ns.flags |= F_ON; else ns.flags &= ~F_ON;
     }
     return false;
+    }
   }
 
   RC_HD void newton(double s0, CellOut* o) {
@@ -418,8 +515,13 @@ struct CellSolver {
     double te = T_e, ti = T_i, lte = s0 * (1.0 / kLn10);
     for (int k = 0; k < 16; ++k) {
       double q, dq, dlx, dlz;
-      q_rad(te, lte, te >= P.T_floor, &q, &dq);
-      const double K = kcoul(axis_coord(lte, P.ax[4]), ti, &dlx, &dlz);
+      const bool on = te >= Tf();
+      const Coord cT = axis_coord(lte, P.ax[1]);
+      const Coord ce = axis_coord(lte, P.ax[4]);
+      const Coord ci = axis_coord(flog10(ti), P.ax[5]);
+      gather(cT, ce, ci, on);
+      q_rad(te, cT, on, &q, &dq);
+      const double K = kcoul_at(ce, ci, &dlx, &dlz);
       const double qcc = (ti - te) * K;
       if (k == 0) { o->q_rad = q; o->q_cc = qcc; }
       const double qr = fmin(q, 0.3 * c * te / h);
@@ -427,7 +529,7 @@ struct CellSolver {
       const double qc = fmin(fmax(qcc, -lim), lim);
       te += h * (qc - qr) / c;
       ti -= h * qc / c;
-      lte = log10(te);
+      lte = flog10(te);
     }
     o->T_e_new = te;
     o->T_i_new = ti;
@@ -436,9 +538,14 @@ struct CellSolver {
   RC_HD void rates(double s0, CellOut* o) {
     const double lte = s0 * (1.0 / kLn10);
     double q, dq, dlx, dlz;
-    q_rad(T_e, lte, T_e >= P.T_floor, &q, &dq);
+    const bool on = T_e >= Tf();
+    const Coord cT = axis_coord(lte, P.ax[1]);
+    const Coord ce = axis_coord(lte, P.ax[4]);
+    const Coord ci = axis_coord(flog10(T_i), P.ax[5]);
+    gather(cT, ce, ci, on);
+    q_rad(T_e, cT, on, &q, &dq);
     o->q_rad = q;
-    o->q_cc = (T_i - T_e) * kcoul(axis_coord(lte, P.ax[4]), T_i, &dlx, &dlz);
+    o->q_cc = (T_i - T_e) * kcoul_at(ce, ci, &dlx, &dlz);
     o->T_e_new = T_e;
     o->T_i_new = T_i;
   }
@@ -468,9 +575,9 @@ struct CellSolver {
       const double* co = P.coef[k];
       y[k] += co[0] + co[1] * fN + co[2] * fT + co[3] * fB;
     }
-    o->q_brem = exp2(y[0]) * invH2;
-    o->q_syn = exp2(y[1]) * invH;
-    o->eta = exp2(y[2]);
+    o->q_brem = fexp2(y[0]) * invH2;
+    o->q_syn = fexp2(y[1]) * invH;
+    o->eta = fexp2(y[2]);
   }
 };
 
@@ -478,7 +585,7 @@ RC_HD bool bad_input(double v) { return !(v > 0.0) || !isfinite(v); }
 
 template <int SCHEME, class Tab>
 RC_HD void cool_cell(const Tab& tab, const StepParams& P, double dt, double n_e, double T_e, double T_i, double B,
-                     double H, bool diag, CellOut* o) {
+                     double H, double floor_gas, bool diag, CellOut* o) {
   if (bad_input(n_e) || bad_input(T_e) || bad_input(T_i) || bad_input(B) || bad_input(H)) {
     const double nan = __builtin_nan("");
     o->T_e_new = o->T_i_new = o->q_rad = o->q_cc = o->q_brem = o->q_syn = o->eta = nan;
@@ -486,7 +593,7 @@ RC_HD void cool_cell(const Tab& tab, const StepParams& P, double dt, double n_e,
     return;
   }
   CellSolver<Tab> cs(tab, P);
-  const double s0 = cs.setup(n_e, T_e, T_i, B, H, dt);
+  const double s0 = cs.setup(n_e, T_e, T_i, B, H, dt, floor_gas);
   o->status = cs.clamp;
   if (SCHEME == SCHEME_NEWTON) {
     cs.newton(s0, o);
@@ -501,15 +608,16 @@ RC_HD void cool_cell(const Tab& tab, const StepParams& P, double dt, double n_e,
 // runtime scheme selection (host self-test path)
 template <class Tab>
 RC_HD void cool_cell_any(const Tab& tab, const StepParams& P, double n_e, double T_e, double T_i, double B,
-                         double H, bool diag, CellOut* o) {
-  if (P.scheme == SCHEME_NEWTON) cool_cell<SCHEME_NEWTON>(tab, P, P.dt, n_e, T_e, T_i, B, H, diag, o);
-  else if (P.scheme == SCHEME_EXPLICIT16) cool_cell<SCHEME_EXPLICIT16>(tab, P, P.dt, n_e, T_e, T_i, B, H, diag, o);
-  else cool_cell<SCHEME_RATES>(tab, P, P.dt, n_e, T_e, T_i, B, H, diag, o);
+                         double H, double floor_gas, bool diag, CellOut* o) {
+  if (P.scheme == SCHEME_NEWTON) cool_cell<SCHEME_NEWTON>(tab, P, P.dt, n_e, T_e, T_i, B, H, floor_gas, diag, o);
+  else if (P.scheme == SCHEME_EXPLICIT16)
+    cool_cell<SCHEME_EXPLICIT16>(tab, P, P.dt, n_e, T_e, T_i, B, H, floor_gas, diag, o);
+  else cool_cell<SCHEME_RATES>(tab, P, P.dt, n_e, T_e, T_i, B, H, floor_gas, diag, o);
 }
 
 // Table-free rates at the input state from the closed forms (DIRECT variant).
 RC_HD void direct_rates(const StepParams& P, double n_e, double T_e, double T_i, double B, double H,
-                        CellOut* o) {
+                        double floor_gas, CellOut* o) {
   if (bad_input(n_e) || bad_input(T_e) || bad_input(T_i) || bad_input(B) || bad_input(H)) {
     const double nan = __builtin_nan("");
     o->T_e_new = o->T_i_new = o->q_rad = o->q_cc = o->q_brem = o->q_syn = o->eta = nan;
@@ -524,11 +632,12 @@ RC_HD void direct_rates(const StepParams& P, double n_e, double T_e, double T_i,
   const double T2 = T_e * T_e;
   const double ta = H * qthin / (4.0 * kSigmaSB * T2 * T2);
   const double ts = 2.0 * n_e * kSigmaT * H;
-  o->q_rad = (T_e < P.T_floor) ? 0.0 : qthin / (1.0 + kSqrt3 * ta + 1.5 * ta * (ta + ts));
+  const bool off = T_e + T_i < floor_gas;
+  o->q_rad = (off || T_e < P.T_floor) ? 0.0 : qthin / (1.0 + kSqrt3 * ta + 1.5 * ta * (ta + ts));
   o->q_cc = (T_i - T_e) * exp(ln_coulomb_coeff(n_e, T_e, T_i, P.ln_lambda));
   o->T_e_new = T_e;
   o->T_i_new = T_i;
-  o->status = 0;
+  o->status = off ? ST_GAS_FLOOR : 0;
 }
 
 }  // namespace rc

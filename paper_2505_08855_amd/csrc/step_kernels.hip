@@ -5,41 +5,64 @@
 // outputs are written once, coalesced.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
+#include <mutex>
 
 #include "radcool.h"
+#include "rc_defer.hpp"
 #include "rc_internal.hpp"
-#include "rc_compact.hpp"
 #include "rc_kernels.hpp"
 
 namespace rc {
 
+// Occupancy target (waves per SIMD) the register allocator works to for
+// each scheme; the Newton solve trades a little spilling for latency hiding.
+#ifndef RC_NEWTON_WAVES
+#define RC_NEWTON_WAVES 2
+#endif
+template <int SCHEME>
+constexpr int kStepWaves = SCHEME == SCHEME_NEWTON ? RC_NEWTON_WAVES : SCHEME == SCHEME_EXPLICIT16 ? 3 : 1;
+
 template <int SCHEME, class Tab>
-__global__ __launch_bounds__(256) void k_step(Tab tab, StepParams P, StateArgs s, OutArgs o, int64_t n) {
+__global__ __launch_bounds__(256, kStepWaves<SCHEME>) void k_step(Tab tab, StepParams P, StateArgs s, OutArgs o,
+                                                                 int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   CellOut r;
   const bool diag = o.Q_brem || o.Q_syn || o.eta;
-  cool_cell<SCHEME>(tab, P, P.dt, s.n_e[i], s.T_e[i], s.T_i[i], s.B[i], s.H[i], diag, &r);
+  cool_cell<SCHEME>(tab, P, P.dt, s.n_e[i], s.T_e[i], s.T_i[i], s.B[i], s.H[i], floor_gas_at(s, i), diag, &r);
   store(o, i, r);
 }
 
-// Newton with in-workgroup compaction: one tile of kTile cells per workgroup
-template <class Tab>
-__global__ __launch_bounds__(kTile) void k_newton_compact(Tab tab, StepParams P, StateArgs s, OutArgs o, int64_t n) {
-  __shared__ ParkedTile L;
-  const int64_t first = (int64_t)blockIdx.x * kTile;
-  const int64_t left = n - first;
-  const int count = left < kTile ? (int)left : kTile;
+// One launch of the Newton solve with straggler deferral: FRESH takes the
+// cells themselves (one per thread), later launches the previous launch's
+// queue (grid-stride over 64-entry chunks); LAST runs everything to completion.
+template <class Tab, bool FRESH, bool LAST>
+__global__ __launch_bounds__(256, RC_NEWTON_WAVES) void k_newton_phase(Tab tab, StepParams P, StateArgs s, OutArgs o,
+                                                                      int64_t n, PhaseArgs q) {
   const bool diag = o.Q_brem || o.Q_syn || o.eta;
-  newton_tile(tab, P, P.dt, first, count, s, o, diag, L);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  int64_t items = n;
+  if (!FRESH) {
+    const unsigned long long c = q.count[q.phase - 1];
+    items = c < (unsigned long long)q.in.cap ? (int64_t)c : q.in.cap;
+  }
+  for (int64_t chunk = wave; chunk * 64 < items; chunk += waves)
+    newton_phase_chunk<Tab, FRESH, LAST>(tab, P, s, o, q, items, chunk, diag);
+}
+
+__global__ void k_zero_counts(unsigned long long* c, int k) {
+  if ((int)threadIdx.x < k) c[threadIdx.x] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_direct(StepParams P, StateArgs s, OutArgs o, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   CellOut r;
-  direct_rates(P, s.n_e[i], s.T_e[i], s.T_i[i], s.B[i], s.H[i], &r);
+  direct_rates(P, s.n_e[i], s.T_e[i], s.T_i[i], s.B[i], s.H[i], floor_gas_at(s, i), &r);
   store(o, i, r);
 }
 
@@ -59,21 +82,105 @@ rc_status make_params(rc_tables t, double dt, const rc_step_opts* o, StepParams*
   P->dt = dt;
   P->T_floor = o->T_floor;
   P->tol = o->tol;
+  P->ln_T_floor = std::log(o->T_floor);
+  P->sqrt_tol = std::sqrt(o->tol);
   P->ln_lambda = t->spec.ln_lambda;
   P->max_iter = o->max_iter;
   P->scheme = o->scheme;
   return RC_OK;
 }
 
-void release_textures(rc_tables_s* t) {
-  for (int k = 0; k < 4; ++k) {
-    if (t->tex[k]) (void)hipDestroyTextureObject(t->tex[k]);
-    if (t->tex_arr[k]) (void)hipFreeArray(t->tex_arr[k]);
-    t->tex[k] = 0;
-    t->tex_arr[k] = nullptr;
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+// Per-call scratch comes from a library-owned stream-ordered pool per device
+// (created on first use); freed blocks stay reserved for the next call, so
+// repeated calls do not return to the driver, and calls on different streams
+// never share scratch.
+hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t hs) {
+  static std::mutex mu;
+  static hipMemPool_t pools[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!pools[dev]) {
+      hipMemPoolProps props = {};
+      props.allocType = hipMemAllocationTypePinned;
+      props.handleTypes = hipMemHandleTypeNone;
+      props.location.type = hipMemLocationTypeDevice;
+      props.location.id = dev;
+      e = hipMemPoolCreate(&pools[dev], &props);
+      if (e != hipSuccess) return e;
+      uint64_t keep = UINT64_MAX;
+      e = hipMemPoolSetAttribute(pools[dev], hipMemPoolAttrReleaseThreshold, &keep);
+      if (e != hipSuccess) return e;
+    }
   }
-  t->tex_ready = false;
+  return hipMallocFromPoolAsync(p, bytes, pools[dev], hs);
 }
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+DeferQueue queue_at(char* base, int64_t cap) {
+  DeferQueue q;
+  q.cap = cap;
+  q.cell = (int64_t*)base;
+  q.v = (double*)(base + align256(sizeof(int64_t) * cap));
+  q.packed = (unsigned*)(base + align256(sizeof(int64_t) * cap) + align256(sizeof(double) * kQueueDoubles * cap));
+  return q;
+}
+
+size_t queue_bytes(int64_t cap) {
+  return align256(sizeof(int64_t) * cap) + align256(sizeof(double) * kQueueDoubles * cap) +
+         align256(sizeof(unsigned) * cap);
+}
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+  return cus;
+}
+
+// The Newton solve over n >= 1 cells as kPhases launches with deferral queues
+// in per-call scratch (two queues used alternately, plus the counters).
+template <class Tab>
+rc_status launch_newton_phased(const Tab& tab, const StepParams& P, const StateArgs& s, const OutArgs& o, int64_t n,
+                               hipStream_t hs) {
+  const int64_t cap = defer_capacity(n);
+  const size_t qb = queue_bytes(cap);
+  void* scratch = nullptr;
+  hipError_t e = scratch_alloc(&scratch, 256 + 2 * qb, hs);
+  if (e != hipSuccess) return hip_fail(e, "rc_cool_step: scratch allocation");
+  char* base = (char*)scratch;
+  unsigned long long* count = (unsigned long long*)base;
+  const DeferQueue qs[2] = {queue_at(base + 256, cap), queue_at(base + 256 + qb, cap)};
+  hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, hs, count, kPhases);
+  const unsigned fresh_grid = (unsigned)((n + 255) / 256);
+  const int64_t later = std::min<int64_t>((cap + 255) / 256, (int64_t)device_cus() * 8);
+  for (int p = 0; p < kPhases; ++p) {
+    const PhaseArgs a{qs[(p + 1) % 2], qs[p % 2], count, p};
+    if (p == 0)
+      hipLaunchKernelGGL((k_newton_phase<Tab, true, false>), dim3(fresh_grid), dim3(256), 0, hs, tab, P, s, o, n, a);
+    else if (p < kPhases - 1)
+      hipLaunchKernelGGL((k_newton_phase<Tab, false, false>), dim3((unsigned)later), dim3(256), 0, hs, tab, P, s, o,
+                         n, a);
+    else
+      hipLaunchKernelGGL((k_newton_phase<Tab, false, true>), dim3((unsigned)later), dim3(256), 0, hs, tab, P, s, o,
+                         n, a);
+  }
+  e = hipGetLastError();
+  const hipError_t fe = hipFreeAsync(scratch, hs);
+  if (e != hipSuccess) return hip_fail(e, "rc_cool_step launch");
+  if (fe != hipSuccess) return hip_fail(fe, "rc_cool_step: scratch release");
+  return RC_OK;
+}
+
+}  // namespace
 
 }  // namespace rc
 
@@ -92,31 +199,39 @@ extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n,
   int variant = opts->variant == RC_VARIANT_AUTO ? RC_VARIANT_GLOBAL : opts->variant;
   if (variant == RC_VARIANT_DIRECT && opts->scheme != RC_SCHEME_RATES)
     return set_error(RC_EUNSUPPORTED, "rc_cool_step: the DIRECT variant evaluates rates only (scheme RC_SCHEME_RATES)");
-  if (variant == RC_VARIANT_LDS || variant == RC_VARIANT_TEX)
+  if (variant == RC_VARIANT_LDS)
     return set_error(RC_EUNSUPPORTED, "rc_cool_step: variant not available in this build");
+  if (variant == RC_VARIANT_TEX)
+    return set_error(RC_EUNSUPPORTED, "rc_cool_step: gfx950 exposes no texture sampling to HIP; plain global "
+                                      "loads already go through the vector L1 cache (use RC_VARIANT_GLOBAL)");
   if (n == 0) return RC_OK;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != t->device)
     return set_error(RC_ESTATE, "rc_cool_step: tables live on another device than the current one");
-  StateArgs s{state->n_e, state->T_e, state->T_i, state->B, state->H};
+  StateArgs s{state->n_e, state->T_e, state->T_i, state->B, state->H, state->T_floor_gas};
   OutArgs o{out->T_e_new, out->T_i_new, out->Q_rad, out->Q_cc, out->Q_brem, out->Q_syn, out->eta, out->status};
   const int block = opts->block ? opts->block : 256;
   const int64_t grid = (n + block - 1) / block;
   if (grid > 0x7fffffffLL) return set_error(RC_EINVAL, "rc_cool_step: n too large for one launch");
   hipStream_t hs = (hipStream_t)stream;
+  // the same launches for every table accessor
+  const auto launch = [&](auto tab) -> rc_status {
+      using Tab = decltype(tab);
+      if (opts->scheme == RC_SCHEME_NEWTON && opts->block == 0)
+        return launch_newton_phased(tab, P, s, o, n, hs);
+      if (opts->scheme == RC_SCHEME_NEWTON)
+        hipLaunchKernelGGL((k_step<SCHEME_NEWTON, Tab>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, n);
+      else if (opts->scheme == RC_SCHEME_EXPLICIT16)
+        hipLaunchKernelGGL((k_step<SCHEME_EXPLICIT16, Tab>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, n);
+      else
+        hipLaunchKernelGGL((k_step<SCHEME_RATES, Tab>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, n);
+      return RC_OK;
+  };
   if (variant == RC_VARIANT_DIRECT) {
     hipLaunchKernelGGL(k_direct, dim3((unsigned)grid), dim3(block), 0, hs, P, s, o, n);
   } else {
-    GlobalTab tab{t->d_cool, t->d_coul, t->spec.cool.n[1], t->spec.cool.n[2], t->spec.coul.n[1], t->spec.coul.n[2]};
-    if (opts->scheme == RC_SCHEME_NEWTON && opts->block == 0)
-      hipLaunchKernelGGL(k_newton_compact<GlobalTab>, dim3((unsigned)((n + kTile - 1) / kTile)), dim3(kTile), 0, hs,
-                         tab, P, s, o, n);
-    else if (opts->scheme == RC_SCHEME_NEWTON)
-      hipLaunchKernelGGL((k_step<SCHEME_NEWTON, GlobalTab>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, n);
-    else if (opts->scheme == RC_SCHEME_EXPLICIT16)
-      hipLaunchKernelGGL((k_step<SCHEME_EXPLICIT16, GlobalTab>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, n);
-    else
-      hipLaunchKernelGGL((k_step<SCHEME_RATES, GlobalTab>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, n);
+    st = with_tab(t, launch);
+    if (st != RC_OK) return st;
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "rc_cool_step launch");

@@ -18,7 +18,7 @@ STATUS_NAMES = {-1: "RC_EINVAL", -2: "RC_ENOMEM", -3: "RC_EDEVICE", -4: "RC_EUNS
                 -5: "RC_ESTATE", -6: "RC_EIO"}
 
 TAB_BREM, TAB_SYNCH, TAB_ETA, TAB_COUL = 0, 1, 2, 3
-ST_INVALID, ST_CLAMP_COOL, ST_CLAMP_COUL, ST_FLOOR, ST_MAXITER = 1, 2, 4, 8, 16
+ST_INVALID, ST_CLAMP_COOL, ST_CLAMP_COUL, ST_FLOOR, ST_MAXITER, ST_GAS_FLOOR = 1, 2, 4, 8, 16, 32
 SCHEME_NEWTON, SCHEME_EXPLICIT16, SCHEME_RATES = 0, 1, 2
 VARIANT_AUTO, VARIANT_GLOBAL, VARIANT_LDS, VARIANT_TEX, VARIANT_DIRECT = 0, 1, 2, 3, 4
 VARIANTS = {"auto": 0, "global": 1, "lds": 2, "tex": 3, "direct": 4}
@@ -29,7 +29,8 @@ EXPORTED = ("rc_default_spec", "rc_default_opts", "rc_build_tables", "rc_tables_
             "rc_tables_destroy", "rc_cool_step", "rc_constants", "rc_selftest_node_host",
             "rc_selftest_special_host", "rc_selftest_step_host", "rc_last_error",
             "rc_cool_step_backward", "rc_selftest_backward_host", "rc_cool_step_batched",
-            "rc_plan_create", "rc_plan_launch", "rc_plan_info", "rc_plan_destroy")
+            "rc_plan_create", "rc_plan_launch", "rc_plan_info", "rc_plan_destroy",
+            "rc_disk_inputs", "rc_rad_pressure_correction", "rc_selftest_disk_host", "rc_selftest_radp_host")
 MAX_STATES = 64
 
 
@@ -43,12 +44,23 @@ class Axes(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
 
 
+VALUE_DTYPES = {"f32": 0, "bf16": 1}
+
+
 class TableSpec(ctypes.Structure):
-    _fields_ = [("cool", Axes), ("coul", Axes), ("ln_lambda", ctypes.c_double)]
+    _fields_ = [("cool", Axes), ("coul", Axes), ("ln_lambda", ctypes.c_double),
+                ("value_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class State(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_void_p) for f in ("n_e", "T_e", "T_i", "B", "H")]
+    _fields_ = [(f, ctypes.c_void_p) for f in ("n_e", "T_e", "T_i", "B", "H", "T_floor_gas")]
+
+
+def _state(state):
+    """rc_state from a dict of device tensors (T_floor_gas optional)."""
+    fl = state.get("T_floor_gas")
+    return State(*[state[k].data_ptr() for k in ("n_e", "T_e", "T_i", "B", "H")],
+                 fl.data_ptr() if fl is not None else None)
 
 
 class Out(ctypes.Structure):
@@ -66,6 +78,11 @@ class Cotangent(ctypes.Structure):
 
 class Grad(ctypes.Structure):
     _fields_ = [(f, ctypes.c_void_p) for f in ("n_e", "T_e", "T_i", "B", "H", "tables")]
+
+
+class DiskParams(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("spin", ctypes.c_double), ("h_floor", ctypes.c_double),
+                ("r_g", ctypes.c_double)]
 
 
 class Block(ctypes.Structure):
@@ -106,7 +123,7 @@ def lib():
             "rc_constants": (i32, [vp, i32]),
             "rc_selftest_node_host": (i32, [P(TableSpec), i32, i32, i32, i32, P(dbl)]),
             "rc_selftest_special_host": (i32, [i32, vp, vp, i64]),
-            "rc_selftest_step_host": (i32, [P(TableSpec), vp, vp, vp, vp, vp, vp, vp, i64, dbl,
+            "rc_selftest_step_host": (i32, [P(TableSpec), vp, vp, vp, vp, vp, vp, vp, vp, i64, dbl,
                                             P(StepOpts), vp, vp, vp, vp, vp]),
             "rc_last_error": (ctypes.c_char_p, []),
             "rc_cool_step_backward": (i32, [vp, P(State), i64, dbl, P(StepOpts), P(Fwd), P(Cotangent), P(Grad), vp]),
@@ -117,6 +134,10 @@ def lib():
             "rc_plan_launch": (i32, [vp, vp]),
             "rc_plan_info": (i32, [vp, P(i32), P(i32), P(dbl)]),
             "rc_plan_destroy": (i32, [vp]),
+            "rc_disk_inputs": (i32, [vp, vp, vp, vp, i64, P(DiskParams), vp, vp, vp]),
+            "rc_rad_pressure_correction": (i32, [vp, vp, vp, i64, dbl, vp, vp, vp]),
+            "rc_selftest_disk_host": (i32, [vp, vp, vp, vp, i64, P(DiskParams), vp, vp]),
+            "rc_selftest_radp_host": (i32, [vp, vp, vp, i64, dbl, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -131,13 +152,15 @@ def check(code):
         raise RadcoolError(code, lib().rc_last_error().decode())
 
 
-def default_spec(n=64):
+def default_spec(n=64, value_dtype="f32"):
+    """Default axes with n nodes each; value_dtype 'f32' or 'bf16' residual storage."""
     s = TableSpec()
     check(lib().rc_default_spec(ctypes.byref(s), n))
+    s.value_dtype = VALUE_DTYPES[value_dtype]
     return s
 
 
-def spec_from_axes(cool, coul, ln_lambda=20.0):
+def spec_from_axes(cool, coul, ln_lambda=20.0, value_dtype="f32"):
     """Build a TableSpec from two sequences of (n, lo, hi) triples."""
     s = TableSpec()
     for dst, src in ((s.cool, cool), (s.coul, coul)):
@@ -146,6 +169,7 @@ def spec_from_axes(cool, coul, ln_lambda=20.0):
             dst.lo[k] = float(lo)
             dst.hi[k] = float(hi)
     s.ln_lambda = ln_lambda
+    s.value_dtype = VALUE_DTYPES[value_dtype]
     return s
 
 
@@ -253,15 +277,18 @@ def _ptr(t):
 def _check_state(state):
     import torch
     ref = state["n_e"]
-    for k in ("n_e", "T_e", "T_i", "B", "H"):
-        t = state[k]
+    for k in ("n_e", "T_e", "T_i", "B", "H", "T_floor_gas"):
+        t = state.get(k)
+        if t is None and k == "T_floor_gas":
+            continue
         if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != ref.numel():
             raise ValueError("state field %s must be a contiguous float64 HIP tensor of equal length" % k)
     return ref.numel()
 
 
 def cool_step(tables, state, dt, opts=None, out=None, diagnostics=False, stream=None):
-    """One cooling step.  ``state``: dict of float64 device tensors n_e, T_e, T_i, B, H.
+    """One cooling step.  ``state``: dict of float64 device tensors n_e, T_e, T_i, B, H
+    and optionally T_floor_gas (per-cell gas-temperature floor, K).
 
     Returns a dict of output tensors (allocated here unless ``out`` supplies them):
     T_e_new, T_i_new, Q_rad, Q_cc, status (+ Q_brem, Q_syn, eta with diagnostics).
@@ -276,7 +303,7 @@ def cool_step(tables, state, dt, opts=None, out=None, diagnostics=False, stream=
         if diagnostics:
             for k in ("Q_brem", "Q_syn", "eta"):
                 out[k] = torch.empty(n, dtype=torch.float64, device=dev)
-    st = State(*[state[k].data_ptr() for k in ("n_e", "T_e", "T_i", "B", "H")])
+    st = _state(state)
     o = Out(*[out[k].data_ptr() if out.get(k) is not None else None
               for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc", "status", "Q_brem", "Q_syn", "eta")])
     check(lib().rc_cool_step(tables.handle, ctypes.byref(st), n, float(dt), ctypes.byref(opts),
@@ -295,7 +322,7 @@ def cool_step_backward(tables, state, dt, fwd, cot, opts=None, table_grad=None, 
     opts = opts or default_opts()
     dev = state["n_e"].device
     g = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("n_e", "T_e", "T_i", "B", "H")}
-    st = State(*[state[k].data_ptr() for k in ("n_e", "T_e", "T_i", "B", "H")])
+    st = _state(state)
     fw = Fwd(*[fwd[k].data_ptr() if fwd is not None and fwd.get(k) is not None else None
                for k in ("T_e_new", "T_i_new", "status")])
     ct = Cotangent(*[cot[k].contiguous().data_ptr() if cot.get(k) is not None else None
@@ -333,7 +360,7 @@ def cool_step_batched(tables, state, blocks_dev, n_blocks, dt_per_state, opts=No
     opts = opts or default_opts()
     out = out if out is not None else _alloc_out(n, state["n_e"].device)
     dts = np.ascontiguousarray(dt_per_state, dtype=np.float64)
-    st = State(*[state[k].data_ptr() for k in ("n_e", "T_e", "T_i", "B", "H")])
+    st = _state(state)
     check(lib().rc_cool_step_batched(tables.handle, ctypes.byref(st), n, ctypes.c_void_p(blocks_dev.data_ptr()),
                                      n_blocks, dts.ctypes.data_as(ctypes.c_void_p), dts.size, ctypes.byref(opts),
                                      ctypes.byref(_out_struct(out)), _stream_ptr(stream)))
@@ -350,7 +377,7 @@ class Plan:
         self.out = out if out is not None else _alloc_out(n, state["n_e"].device)
         self._keep = (tables, state, blocks_dev)      # the plan holds pointers into these
         dts = np.ascontiguousarray(dt_per_state, dtype=np.float64)
-        st = State(*[state[k].data_ptr() for k in ("n_e", "T_e", "T_i", "B", "H")])
+        st = _state(state)
         h = ctypes.c_void_p()
         check(lib().rc_plan_create(tables.handle, ctypes.byref(st), n, ctypes.c_void_p(blocks_dev.data_ptr()),
                                    n_blocks, dts.ctypes.data_as(ctypes.c_void_p), dts.size, ctypes.byref(self.opts),
@@ -413,7 +440,10 @@ def selftest_step_host(spec, resid, coeffs, cells, dt, opts=None):
     outs = {k: np.empty(n) for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")}
     outs["status"] = np.empty(n, dtype=np.uint8)
     P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
-    check(lib().rc_selftest_step_host(ctypes.byref(spec), P(resid), P(coeffs), *[P(a) for a in arrs], n,
+    fl = cells.get("T_floor_gas")
+    fl = None if fl is None else np.ascontiguousarray(fl, dtype=np.float64)
+    check(lib().rc_selftest_step_host(ctypes.byref(spec), P(resid), P(coeffs), *[P(a) for a in arrs],
+                                      P(fl) if fl is not None else None, n,
                                       float(dt), ctypes.byref(opts),
                                       P(outs["T_e_new"]), P(outs["T_i_new"]), P(outs["Q_rad"]),
                                       P(outs["Q_cc"]), P(outs["status"])))
@@ -439,3 +469,68 @@ def selftest_backward_host(spec, resid, coeffs, cells, fwd, cot, dt, opts=None):
                                           *[P(a) for a in fw], *[P(a) for a in ct], n, float(dt), ctypes.byref(opts),
                                           *[P(g[k]) for k in ("n_e", "T_e", "T_i", "B", "H")], P(gt)))
     return g, gt
+
+
+# ---------------------------------------------------------------- upstream inputs and post-processing
+
+TAU_CRIT = 4.6      # e^-tau = 0.01: fewer than 1 % of photons escape unscattered
+
+
+def disk_params(gamma=5.0 / 3.0, spin=0.9375, h_floor=0.1, r_g=None):
+    """Disk parameters (defaults: the paper's runs, M = 10 M_sun)."""
+    if r_g is None:
+        from . import workloads
+        r_g = workloads.R_G
+    return DiskParams(gamma, spin, h_floor, r_g)
+
+
+def disk_inputs(prims, params=None, stream=None):
+    """H_th [cm] and T_floor_gas [K] per cell from device tensors rho, P, u, r
+    (dict).  Returns a dict of two new tensors."""
+    import torch
+    params = params or disk_params()
+    ref = prims["rho"]
+    n = ref.numel()
+    for k in ("rho", "P", "u", "r"):
+        t = prims[k]
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+            raise ValueError("%s must be a contiguous float64 HIP tensor of equal length" % k)
+    out = {k: torch.empty(n, dtype=torch.float64, device=ref.device) for k in ("H_th", "T_floor_gas")}
+    check(lib().rc_disk_inputs(*[prims[k].data_ptr() for k in ("rho", "P", "u", "r")], n, ctypes.byref(params),
+                               out["H_th"].data_ptr(), out["T_floor_gas"].data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+def rad_pressure_correction(n_e, T_e, H, tau_crit=TAU_CRIT, stream=None):
+    """(corrected T_e tensor, uint8 thick flags) for float64 device tensors."""
+    import torch
+    n = n_e.numel()
+    for t in (n_e, T_e, H):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+            raise ValueError("inputs must be contiguous float64 HIP tensors of equal length")
+    T = torch.empty_like(T_e)
+    thick = torch.empty(n, dtype=torch.uint8, device=T_e.device)
+    check(lib().rc_rad_pressure_correction(n_e.data_ptr(), T_e.data_ptr(), H.data_ptr(), n, float(tau_crit),
+                                           T.data_ptr(), thick.data_ptr(), _stream_ptr(stream)))
+    return T, thick
+
+
+def selftest_disk_host(rho, P, u, r, params=None):
+    """rc_disk_inputs' per-cell code on the host (test use)."""
+    params = params or disk_params()
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (rho, P, u, r)]
+    H = np.empty_like(a[0])
+    Tf = np.empty_like(a[0])
+    ptr = lambda v: v.ctypes.data_as(ctypes.c_void_p)
+    check(lib().rc_selftest_disk_host(*[ptr(v) for v in a], a[0].size, ctypes.byref(params), ptr(H), ptr(Tf)))
+    return H, Tf
+
+
+def selftest_radp_host(n_e, T_e, H, tau_crit=TAU_CRIT):
+    """rc_rad_pressure_correction's per-cell code on the host (test use)."""
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (n_e, T_e, H)]
+    T = np.empty_like(a[0])
+    thick = np.empty(a[0].size, dtype=np.uint8)
+    ptr = lambda v: v.ctypes.data_as(ctypes.c_void_p)
+    check(lib().rc_selftest_radp_host(*[ptr(v) for v in a], a[0].size, float(tau_crit), ptr(T), ptr(thick)))
+    return T, thick

@@ -103,18 +103,18 @@ def test_selftest_argument_checks(L):
     v = ctypes.c_double()
     assert L.rc_selftest_node_host(ctypes.byref(s), 4, 0, 0, 0, ctypes.byref(v)) == -1
     assert L.rc_selftest_node_host(ctypes.byref(s), 0, 8, 0, 0, ctypes.byref(v)) == -1
-    assert L.rc_selftest_special_host(9, None, None, 1) == -1
+    assert L.rc_selftest_special_host(10, None, None, 1) == -1
     op = R.default_opts(max_iter=0)
     x = np.ones(1)
     resid = np.zeros(4 * 512, dtype=np.float32)
     co = np.zeros(16)
     P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
     for bad_dt in (0.0, -1.0, float("nan"), float("inf")):
-        assert L.rc_selftest_step_host(ctypes.byref(s), P(resid), P(co), *[P(x)] * 5, 1, bad_dt,
+        assert L.rc_selftest_step_host(ctypes.byref(s), P(resid), P(co), *[P(x)] * 5, None, 1, bad_dt,
                                        ctypes.byref(R.default_opts()), None, None, None, None, None) == -1
-    assert L.rc_selftest_step_host(ctypes.byref(s), P(resid), P(co), *[P(x)] * 5, 1, 1e-8,
+    assert L.rc_selftest_step_host(ctypes.byref(s), P(resid), P(co), *[P(x)] * 5, None, 1, 1e-8,
                                    ctypes.byref(op), None, None, None, None, None) == -1
     for field, val in (("scheme", 7), ("variant", 9), ("T_floor", -1.0), ("tol", 0.0), ("block", 96)):
         op = R.default_opts(**{field: val})
-        assert L.rc_selftest_step_host(ctypes.byref(s), P(resid), P(co), *[P(x)] * 5, 1, 1e-8,
+        assert L.rc_selftest_step_host(ctypes.byref(s), P(resid), P(co), *[P(x)] * 5, None, 1, 1e-8,
                                        ctypes.byref(op), None, None, None, None, None) == -1, field

@@ -280,18 +280,45 @@ def test_full_size_iid256_sampled(dev, oracle128):
     assert int((out["status"] & R.ST_MAXITER).sum()) == 0
 
 
-def test_compacted_newton_equals_plain_kernel(dev, imported64):
-    """The default Newton kernel parks unfinished cells in LDS between rounds
-    (in-workgroup compaction); a plain one-cell-per-thread launch (explicit
-    block size) runs the same per-cell steps.  Multiply-adds may be fused
-    differently in the two kernels, so values agree to rounding, and a cell
-    parked in the wrong slot would show up as a gross mismatch."""
+@pytest.mark.parametrize("n,dt_scale", [(100_003, 1.0), (100_003, 1e3), (1, 1.0), (63, 1e3), (65, 1e3),
+                                         (4099, 1e3)])
+def test_deferred_newton_equals_plain_kernel(dev, imported64, n, dt_scale):
+    """The default Newton launch sets stragglers aside in a queue and resumes
+    them in later launches (straggler deferral); a plain one-cell-per-thread
+    launch (explicit block size) runs the same per-cell steps.  Multiply-adds
+    may be fused differently in the two kernels, so values agree to rounding;
+    a state resumed for the wrong cell would show up as a gross mismatch.
+    The stiff step (dt x 1e3) defers most cells, several launches deep; the
+    ragged sizes leave partial waves in every launch."""
     gt, _ = imported64
-    cells = W.workload(3, n=100_003)
+    cells = W.workload(3, n=n)
     st = to_dev(cells, dev)
-    a = {k: v.cpu().numpy() for k, v in R.cool_step(gt, st, DT, R.default_opts(), diagnostics=True).items()}
-    b = {k: v.cpu().numpy() for k, v in R.cool_step(gt, st, DT, R.default_opts(block=256),
+    dt = DT * dt_scale
+    a = {k: v.cpu().numpy() for k, v in R.cool_step(gt, st, dt, R.default_opts(), diagnostics=True).items()}
+    b = {k: v.cpu().numpy() for k, v in R.cool_step(gt, st, dt, R.default_opts(block=256),
                                                      diagnostics=True).items()}
     assert np.array_equal(a["status"], b["status"])
     for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc", "Q_brem", "Q_syn", "eta"):
         assert np.max(rel_err(a[k], b[k])) < 1e-12, k
+
+
+@pytest.mark.parametrize("block", [0, 256])
+def test_gas_floor_energy_tier(dev, imported64, spec64, block):
+    """Per-cell gas-temperature floor: cells below it take the step with
+    radiative cooling off (status 32), through the deferred launches and the
+    plain kernel."""
+    from oracle import upstream as U
+    gt, stored = imported64
+    cells = W.workload(0)
+    arr = [cells[f] for f in W.FIELDS]
+    floor = np.median(arr[1] + arr[2]) * np.ones_like(arr[0])
+    dt = 1e3 * DT
+    st = to_dev(cells, dev)
+    st["T_floor_gas"] = torch.from_numpy(floor).to(dev)
+    out = to_np(R.cool_step(gt, st, dt, R.default_opts(block=block)))
+    ref = U.step_with_gas_floor(S.TableSet(spec64, stored), *arr, dt, floor)
+    assert np.array_equal(out["status"], ref["status"])
+    off = (out["status"] & R.ST_GAS_FLOOR) != 0
+    assert 0.3 < off.mean() < 0.7 and np.all(out["Q_rad"][off] == 0.0)
+    for k in ("T_e_new", "T_i_new"):
+        assert np.max(rel_err(out[k], ref[k])) < ENERGY_TOL, k

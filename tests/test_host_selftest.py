@@ -38,6 +38,37 @@ def test_tail_integral_and_root():
     assert np.max(rel_err(R.selftest_special_host(4, lr), P.solve_xc(lr))) < 1e-13
 
 
+def _ulps(got, ref):
+    return np.max(np.abs(got - ref) / np.spacing(np.abs(ref)))
+
+
+def test_solver_elementary_functions():
+    """The solver's own ln, log10, log1p, exp, exp2 against the C library:
+    a few ulp over the whole double range, exact special cases."""
+    rng = np.random.default_rng(11)
+    x = np.concatenate([10 ** rng.uniform(-307, 308, 100000), rng.uniform(0.5, 2.0, 50000),
+                        1.0 + rng.uniform(-1e-8, 1e-8, 5000), [5e-324, 2.2250738585072014e-308, 1.0, 2.0, 0.5]])
+    assert _ulps(R.selftest_special_host(5, x), np.log(x)) <= 2
+    assert _ulps(R.selftest_special_host(6, x), np.log10(x)) <= 4
+    v = np.concatenate([rng.uniform(-0.999999, 1e3, 50000), 10 ** rng.uniform(-300, -1, 50000),
+                        -(10 ** rng.uniform(-300, -1, 50000)), 10 ** rng.uniform(0, 300, 5000)])
+    assert _ulps(R.selftest_special_host(7, v), np.log1p(v)) <= 4
+    assert np.array_equal(R.selftest_special_host(5, np.array([1.0])), [0.0])
+    assert np.array_equal(R.selftest_special_host(7, np.array([0.0, 1e-300])), [0.0, 1e-300])
+    s = np.concatenate([rng.uniform(-699, 699, 100000), rng.uniform(-1e-3, 1e-3, 5000), [0.0, 1.0, -1.0]])
+    assert _ulps(R.selftest_special_host(8, s), np.exp(s)) <= 2
+    y = np.concatenate([rng.uniform(-1020, 1020, 100000), rng.uniform(-1.0, 1.0, 5000), [0.0, 0.5, -0.5, 1023.5]])
+    assert _ulps(R.selftest_special_host(9, y), np.exp2(y)) <= 2
+    # powers of two and e^0 are exact
+    k = np.arange(-1000, 1001, dtype=np.float64)
+    assert np.array_equal(R.selftest_special_host(9, k), np.exp2(k))
+    # outside |s| < 700 exp takes the library path: overflow, underflow, inf, NaN
+    e = np.array([-np.inf, np.inf, 800.0, -800.0, 709.5])
+    with np.errstate(over="ignore"):
+        assert np.array_equal(R.selftest_special_host(8, e), np.exp(e))
+    assert np.isnan(R.selftest_special_host(8, np.array([np.nan])))[0]
+
+
 @pytest.mark.parametrize("n", [64, 128])
 def test_node_values_match_oracle(n):
     spec = R.default_spec(n)
@@ -159,3 +190,63 @@ def test_backward_matches_oracle_gradient_on_host(spec64, storage64, cells0_smal
         want = ref["tables"][name].ravel()
         got = gt[k * vc:(k + 1) * vc]
         assert np.max(np.abs(got - want)) <= 1e-9 * np.max(np.abs(want)), name
+
+
+@pytest.mark.parametrize("scheme", ["newton", "explicit16"])
+def test_step_gas_floor_on_host(spec64, storage64, cells0_small, scheme):
+    """Per-cell gas-temperature floor: cells whose input T_e + T_i lies below it
+    take the step with radiative cooling off (status bit 32)."""
+    from oracle import upstream as U
+    resid, coeffs, stored = storage64
+    ts = S.TableSet(spec64, stored)
+    arr = [cells0_small[f] for f in W.FIELDS]
+    floor = np.median(arr[1] + arr[2]) * np.ones_like(arr[0])
+    dt = 1e3 * DT
+    ref = U.step_with_gas_floor(ts, *arr, dt, floor, scheme="be" if scheme == "newton" else "ex16")
+    cells = dict(cells0_small)
+    cells["T_floor_gas"] = floor
+    got = R.selftest_step_host(R.default_spec(64), resid, coeffs, cells, dt, R.default_opts(scheme=scheme))
+    assert np.array_equal(got["status"], ref["status"])
+    off = (got["status"] & 32) != 0
+    assert 0.3 < off.mean() < 0.7
+    assert np.all(got["Q_rad"][off] == 0.0)
+    tol = 1e-9 if scheme == "newton" else 1e-11
+    for k in ("T_e_new", "T_i_new"):
+        assert np.max(rel_err(got[k], ref[k])) < tol, k
+
+
+def _prims(n, seed):
+    rng = np.random.default_rng(seed)
+    rho = 10 ** rng.uniform(-14, -2, n)
+    theta = 10 ** rng.uniform(-6, 0.5, n)             # P / (rho c^2), up to relativistic
+    P = theta * rho * 2.99792458e10 ** 2
+    u = P / (5.0 / 3.0 - 1.0)
+    r = 10 ** rng.uniform(0.2, 3, n)
+    return rho, P, u, r
+
+
+def test_disk_inputs_on_host():
+    from oracle import upstream as U
+    rho, P, u, r = _prims(4000, 5)
+    prm = R.disk_params()
+    H, Tf = R.selftest_disk_host(rho, P, u, r, prm)
+    assert np.max(rel_err(H, U.scale_height(rho, P, u, r, prm.spin, prm.gamma, prm.r_g))) < 1e-14
+    assert np.max(rel_err(Tf, U.floor_temperature(r, prm.spin, prm.h_floor))) < 1e-14
+    bad = [np.array([v]) for v in (-1.0, 1.0, 1.0, 1.0)]
+    assert np.isnan(R.selftest_disk_host(*bad, prm)[0][0])
+    with pytest.raises(R.RadcoolError):
+        R.selftest_disk_host(rho, P, u, r, R.disk_params(gamma=1.0))
+
+
+def test_rad_pressure_correction_on_host():
+    from oracle import upstream as U
+    rng = np.random.default_rng(6)
+    n = 4000
+    n_e = 10 ** rng.uniform(14, 24, n)
+    T_e = 10 ** rng.uniform(5, 10, n)
+    H = 10 ** rng.uniform(5, 9, n)
+    T, thick = R.selftest_radp_host(n_e, T_e, H)
+    ref, rthick = U.rad_pressure_temperature(n_e, T_e, T_e, H)
+    assert np.array_equal(thick.astype(bool), rthick)
+    assert np.max(rel_err(T, ref)) < 1e-14
+    assert np.isnan(R.selftest_radp_host(np.array([0.0]), np.array([1e6]), np.array([1e6]))[0][0])

@@ -103,3 +103,29 @@ def test_quantized_storage_error_bound(tables64):
         # float32 rounding of the residual: half an ulp of |residual|
         bound = np.abs(resid.astype(np.float64)) * 2.0 ** -24 + 1e-12
         assert np.all(err <= bound), name
+
+
+def test_bf16_rounding_ties_to_even_and_matches_torch():
+    one = 1.0
+    cases = {one: one,
+             one + 2.0 ** -8: one,                              # tie, even neighbour is 1
+             one + 3 * 2.0 ** -8: one + 2.0 ** -6,              # tie, rounds up to even
+             one + 2.0 ** -8 + 2.0 ** -20: one + 2.0 ** -7,     # just above the tie
+             -(one + 2.0 ** -8 + 2.0 ** -20): -(one + 2.0 ** -7),
+             0.0: 0.0, 2.0 ** -100: 2.0 ** -100}
+    got = T.round_bf16(np.array(list(cases), dtype=np.float32))
+    assert np.array_equal(got, np.array(list(cases.values()), dtype=np.float32))
+    torch = pytest.importorskip("torch")
+    a = np.random.default_rng(9).normal(0.0, 30.0, 200000).astype(np.float32)
+    ref = torch.from_numpy(a).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(T.round_bf16(a), ref)
+
+
+def test_bf16_storage_error_bound(tables64):
+    for name in T.TABLE_NAMES:
+        co, resid, stored = T.quantize(tables64[name], "bf16")
+        assert np.array_equal(resid, T.round_bf16(resid))
+        err = np.abs(stored - tables64[name])
+        # bfloat16 keeps 8 significant bits: half an ulp is 2^-9 relative, plus the float32 step
+        bound = np.abs(resid.astype(np.float64)) * (2.0 ** -8 + 2.0 ** -24) + 1e-12
+        assert np.all(err <= bound), name

@@ -1,0 +1,84 @@
+"""Pins of the upstream inputs (scale height, temperature floor) and of the
+radiation-pressure temperature correction (Sec. II.F, III.B.2, IV)."""
+import numpy as np
+
+from conftest import rel_err
+from oracle import constants as K
+from oracle import upstream as U
+
+M = 10.0 * K.M_SUN
+R_G = K.G_NEWTON * M / K.C_LIGHT ** 2
+
+
+def test_keplerian_frequency_is_keplers_law_for_zero_spin():
+    r = np.array([2.0, 6.0, 10.0, 100.0, 1000.0])
+    omega_cgs = U.omega_k(r, 0.0) * K.C_LIGHT / R_G
+    assert np.max(rel_err(omega_cgs, np.sqrt(K.G_NEWTON * M / (r * R_G) ** 3))) < 1e-12
+    # prograde spin lowers the frequency at fixed r
+    assert np.all(U.omega_k(r, 0.9375) < U.omega_k(r, 0.0))
+
+
+def test_scale_height_nonrelativistic_limit():
+    rng = np.random.default_rng(1)
+    rho = 10 ** rng.uniform(-12, -4, 100)
+    theta = 10 ** rng.uniform(-9, -7, 100)          # P / (rho c^2) << 1
+    P = theta * rho * K.C_LIGHT ** 2
+    u = 1.5 * P
+    r = 10 ** rng.uniform(0.4, 3, 100)
+    H = U.scale_height(rho, P, u, r, 0.0, 5.0 / 3.0, R_G)
+    omega = np.sqrt(K.G_NEWTON * M / (r * R_G) ** 3)
+    H_newton = np.sqrt(5.0 / 3.0 * P / rho) / omega
+    assert np.max(rel_err(H, H_newton)) < 1e-6
+
+
+def test_sound_speed_of_radiation_like_gas():
+    # rho -> 0 with u = 3 P and gamma = 4/3: c_s^2 = gamma P / (u + P) = 1/3
+    P = np.array([1.0, 1e5])
+    H = U.scale_height(np.zeros(2), P, 3.0 * P, np.array([10.0, 10.0]), 0.0, 4.0 / 3.0, R_G)
+    cs = H * U.omega_k(10.0, 0.0) / R_G
+    assert np.max(rel_err(cs, np.sqrt(1.0 / 3.0))) < 1e-14
+
+
+def test_floor_temperature_gives_the_floor_thickness():
+    # a gas at the floor temperature (P / rho = k T_gas / (m_p c^2)) has an
+    # isothermal scale height H / R = h_floor sqrt(pi / 2) in the cold limit;
+    # the enthalpy (rho c^2 + u + P) lowers c_s by about 1.25 theta, theta = P / (rho c^2)
+    r = np.array([5.0, 30.0, 300.0, 3000.0])
+    Tf = U.floor_temperature(r, 0.0, 0.1)
+    rho = np.full(4, 1e-10)
+    P = rho * K.K_B * Tf / K.M_P
+    theta = P / (rho * K.C_LIGHT ** 2)
+    H = U.scale_height(rho, P, 1.5 * P, r, 0.0, 1.0, R_G)
+    err = rel_err(H / (r * R_G), 0.1 * np.sqrt(np.pi / 2.0))
+    assert np.all(err < 2.0 * theta) and np.all(err > 0.5 * theta)
+    assert np.all(np.diff(Tf) < 0)                 # hotter floor closer in
+
+
+def test_radiation_constant_near_printed_value():
+    # the paper prints a = 7.5646e-15; 4 sigma_SB / c with CODATA values differs by 1.4e-4
+    assert abs(U.A_RAD / 7.5646e-15 - 1.0) < 2e-4
+
+
+def test_rad_pressure_correction_limits_and_residual():
+    rng = np.random.default_rng(2)
+    n = 2000
+    n_e = 10 ** rng.uniform(14, 24, n)
+    T_e = 10 ** rng.uniform(5, 10, n)
+    T_i = T_e * 10 ** rng.uniform(0, 1, n)
+    H = 10 ** rng.uniform(5, 9, n)
+    T, thick = U.rad_pressure_temperature(n_e, T_e, T_i, H)
+    tau = n_e * K.SIGMA_T * H
+    assert np.array_equal(thick, tau > 4.6)
+    assert np.array_equal(T[~thick], T_e[~thick])
+    t = T[thick]
+    res = U.A_RAD * t ** 4 + n_e[thick] * K.K_B * t - n_e[thick] * K.K_B * T_e[thick]
+    assert np.max(np.abs(res) / (n_e[thick] * K.K_B * T_e[thick])) < 1e-13
+    assert np.all(t < T_e[thick])
+    gas = U.A_RAD * T_e ** 3 < 1e-6 * n_e * K.K_B      # radiation negligible
+    assert np.max(rel_err(T[thick & gas], T_e[thick & gas])) < 2e-6
+    rad = U.A_RAD * T_e ** 3 > 1e6 * n_e * K.K_B       # radiation dominated
+    m = thick & rad
+    assert m.sum() > 10
+    # T^4 = (n k / a)(T_e - T): the leading correction is T / (4 T_e) ~ (n k / (a T_e^3))^(1/4) / 4
+    eps = (n_e[m] * K.K_B / (U.A_RAD * T_e[m] ** 3)) ** 0.25
+    assert np.all(rel_err(T[m], (n_e[m] * K.K_B * T_e[m] / U.A_RAD) ** 0.25) < 0.5 * eps)
