@@ -376,6 +376,30 @@ def main():
                 var[name] = {"ms": vms, "Gcell_per_s": n / (vms * 1e-3) / 1e9}
             except R.RadcoolError as e:
                 var[name] = {"error": str(e)}
+        # the upstream inputs and the radiation-pressure correction over the same
+        # cell count: elementwise kernels, 48 and 33 algorithmic bytes per cell
+        rng = torch.Generator(device=dev).manual_seed(W.SEED_BASE)
+        prims = {"rho": torch.rand(n, dtype=torch.float64, device=dev, generator=rng) * 1e-8 + 1e-12,
+                 "r": torch.rand(n, dtype=torch.float64, device=dev, generator=rng) * 998.0 + 2.0}
+        prims["P"] = prims["rho"] * 1e17
+        prims["u"] = 1.5 * prims["P"]
+        for name, fn, nbytes in (
+                ("disk_inputs", lambda: R.disk_inputs(prims), 48),
+                ("rad_pressure_correction", lambda: R.rad_pressure_correction(state["n_e"], state["T_e"],
+                                                                             state["H"]), 33)):
+            fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            vms = e0.elapsed_time(e1) / 5
+            var[name] = {"ms": vms, "Gcell_per_s": n / (vms * 1e-3) / 1e9,
+                         "hbm_frac": nbytes * n / (vms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del prims
         # the same step reading bfloat16-stored tables (half the table bytes)
         t16 = R.Tables.build(R.default_spec(table_n, "bf16"))
         vms, _ = time_steps(R, torch, t16, state, dt, opts, out, 3, 1)

@@ -321,6 +321,38 @@ rc_status rc_disk_inputs(const double* rho, const double* P, const double* u, co
 rc_status rc_rad_pressure_correction(const double* n_e, const double* T_e, const double* H, int64_t n,
                                      double tau_crit, double* T_e_out, uint8_t* thick, void* stream);
 
+/* The paper's own cooling-table layout (Sec. II.F, III.A), for comparison
+ * with the exact 3-D column tables: log2 of the bridged Q_total on a 4-D grid
+ * over log10 H [cm], log10 B [G], log10 n_e [cm^-3], log10 T_e [K] (node k of
+ * axis d at lo[d] + k (hi[d] - lo[d]) / (n[d] - 1)), stored as plain FP32 log2
+ * values C-ordered [H][B][n_e][T_e], read by 4-D multilinear interpolation
+ * (clamped at the edges).  The paper's flattening of n_e and T_e into one
+ * texture axis is a texture-memory constraint and changes no value. */
+typedef struct {
+  int32_t n[4];
+  double lo[4];
+  double hi[4];
+} rc_axes4;
+typedef struct rc_table4d_s* rc_table4d;
+
+/* The paper's ranges with n points per axis: H in [1e3, 1e12], B in [1, 1e10],
+ * n_e in [1e2, 1e25], T_e in [1e2, 1e15] (the paper: n = 100). */
+rc_status rc_paper_axes4(rc_axes4* axes, int32_t n);
+/* Evaluate every node from the closed forms on the current device
+ * (synchronous; 100^4 nodes take 400 MB of device memory). */
+rc_status rc_build_table4d(const rc_axes4* axes, void* stream, rc_table4d* out);
+/* Create from host FP32 log2 values laid out as above (synchronous). */
+rc_status rc_table4d_import(const rc_axes4* axes, const float* values, void* stream, rc_table4d* out);
+/* Copy the axes and / or the values to host memory (either may be NULL; synchronous). */
+rc_status rc_table4d_export(rc_table4d t, rc_axes4* axes, float* values);
+rc_status rc_table4d_destroy(rc_table4d t);
+/* Q_rad (bridged total cooling, erg cm^-3 s^-1; zero below T_floor) at every
+ * cell from the 4-D table; status (may be NULL) gets RC_ST_INVALID or
+ * RC_ST_CLAMP_COOL.  state->T_i and state->T_floor_gas are not read.
+ * Asynchronous on stream. */
+rc_status rc_rates4d(rc_table4d t, const rc_state* state, int64_t n, double T_floor, double* Q_rad,
+                     uint8_t* status, void* stream);
+
 /* The physical constants compiled into the library, in this order:
  * c, k_B, h, m_e, m_p, e, sigma_T, sigma_SB; returns how many were written
  * (at most n). */
@@ -357,6 +389,14 @@ rc_status rc_selftest_disk_host(const double* rho, const double* P, const double
                                 const rc_disk_params* params, double* H_th, double* T_floor_gas);
 rc_status rc_selftest_radp_host(const double* n_e, const double* T_e, const double* H, int64_t n, double tau_crit,
                                 double* T_e_out, uint8_t* thick);
+
+/* Host-side self-tests of the 4-D table: node values (log2 Q_total at the
+ * given states) and the rates read from host FP32 values.  For tests only. */
+rc_status rc_selftest_node4d_host(const double* H, const double* B, const double* n_e, const double* T, int64_t n,
+                                  double* log2_q);
+rc_status rc_selftest_rates4d_host(const rc_axes4* axes, const float* values, const double* n_e, const double* T_e,
+                                   const double* B, const double* H, int64_t n, double T_floor, double* Q_rad,
+                                   uint8_t* status);
 
 /* Host-side self-test of the per-cell adjoint (same source as the GPU
  * kernel) on tables in storage form (host memory).  Arrays of length n; cot_*

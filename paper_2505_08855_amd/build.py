@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libradcool.so")
 
-SOURCES = ("radcool.hip", "step_kernels.hip", "backward.hip", "batched.hip", "disk.hip")
+SOURCES = ("radcool.hip", "step_kernels.hip", "backward.hip", "batched.hip", "disk.hip", "table4d.hip")
 
 
 def hipcc():

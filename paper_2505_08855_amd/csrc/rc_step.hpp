@@ -474,15 +474,24 @@ struct CellSolver {
       const bool newton_ok = (use3 || ns.dG > 0.0) && (sn == sn);
       if (newton_ok && fabs(sn - s) <= P.sqrt_tol && !(floor_pending && sn < sf)) {
         // converged: Newton converges quadratically, so once the step is
-        // below sqrt(tol) the error left after taking it is O(tol); only
-        // z(x) remains, solved at the new point (cooling off, so that only
-        // the inner solve runs) in this same round, from the first-order
-        // warm start z + dz/dx (x' - x).  Tested before the bracket
-        // safeguard, which could reject a step below an end's ulp.
+        // below sqrt(tol) the error left after taking it is O(tol) -- provided
+        // the step stays inside the table cells of the current iterate (the
+        // interpolant is smooth inside a cell; across a node its slope jumps
+        // and the step's error is first order in the jump).  Then only z(x)
+        // remains, solved at the new point (cooling off, so that only the
+        // inner solve runs) in this same round, from the first-order warm
+        // start z + dz/dx (x' - x).  Tested before the bracket safeguard,
+        // which could reject a step below an end's ulp.
         const double xn = fexp(sn);
-        ns.z += dzdx * (xn - ns.xe);
-        ns.kind = FINAL; ns.se = sn; ns.xe = xn; ns.flags &= ~F_ON;
-        continue;
+        const double zn = ns.z + dzdx * (xn - ns.xe);
+        const double lxn = sn * (1.0 / kLn10);
+        const bool same_cells = (!(ns.flags & F_ON) || axis_coord(lxn, P.ax[1]).i == iT) &&
+                                axis_coord(lxn, P.ax[4]).i == ie && axis_coord(flog10(zn), P.ax[5]).i == ii;
+        if (same_cells) {
+          ns.z = zn;
+          ns.kind = FINAL; ns.se = sn; ns.xe = xn; ns.flags &= ~F_ON;
+          continue;
+        }
       }
       if (floor_pending && (!newton_ok || sn < sf)) {
         // the descent would cross the floor (decided on the raw Newton step:

@@ -30,7 +30,9 @@ EXPORTED = ("rc_default_spec", "rc_default_opts", "rc_build_tables", "rc_tables_
             "rc_selftest_special_host", "rc_selftest_step_host", "rc_last_error",
             "rc_cool_step_backward", "rc_selftest_backward_host", "rc_cool_step_batched",
             "rc_plan_create", "rc_plan_launch", "rc_plan_info", "rc_plan_destroy",
-            "rc_disk_inputs", "rc_rad_pressure_correction", "rc_selftest_disk_host", "rc_selftest_radp_host")
+            "rc_disk_inputs", "rc_rad_pressure_correction", "rc_selftest_disk_host", "rc_selftest_radp_host",
+            "rc_paper_axes4", "rc_build_table4d", "rc_table4d_import", "rc_table4d_export", "rc_table4d_destroy",
+            "rc_rates4d", "rc_selftest_node4d_host", "rc_selftest_rates4d_host")
 MAX_STATES = 64
 
 
@@ -83,6 +85,10 @@ class Grad(ctypes.Structure):
 class DiskParams(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("spin", ctypes.c_double), ("h_floor", ctypes.c_double),
                 ("r_g", ctypes.c_double)]
+
+
+class Axes4(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 4), ("lo", ctypes.c_double * 4), ("hi", ctypes.c_double * 4)]
 
 
 class Block(ctypes.Structure):
@@ -138,6 +144,14 @@ def lib():
             "rc_rad_pressure_correction": (i32, [vp, vp, vp, i64, dbl, vp, vp, vp]),
             "rc_selftest_disk_host": (i32, [vp, vp, vp, vp, i64, P(DiskParams), vp, vp]),
             "rc_selftest_radp_host": (i32, [vp, vp, vp, i64, dbl, vp, vp]),
+            "rc_paper_axes4": (i32, [P(Axes4), i32]),
+            "rc_build_table4d": (i32, [P(Axes4), vp, P(vp)]),
+            "rc_table4d_import": (i32, [P(Axes4), vp, vp, P(vp)]),
+            "rc_table4d_export": (i32, [vp, P(Axes4), vp]),
+            "rc_table4d_destroy": (i32, [vp]),
+            "rc_rates4d": (i32, [vp, P(State), i64, dbl, vp, vp, vp]),
+            "rc_selftest_node4d_host": (i32, [vp, vp, vp, vp, i64, vp]),
+            "rc_selftest_rates4d_host": (i32, [P(Axes4), vp, vp, vp, vp, vp, i64, dbl, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -534,3 +548,91 @@ def selftest_radp_host(n_e, T_e, H, tau_crit=TAU_CRIT):
     ptr = lambda v: v.ctypes.data_as(ctypes.c_void_p)
     check(lib().rc_selftest_radp_host(*[ptr(v) for v in a], a[0].size, float(tau_crit), ptr(T), ptr(thick)))
     return T, thick
+
+
+# ---------------------------------------------------------------- the paper's 4-D table layout
+
+def paper_axes4(n=100):
+    a = Axes4()
+    check(lib().rc_paper_axes4(ctypes.byref(a), n))
+    return a
+
+
+class Table4D:
+    """log2 Q_total(H, B, n_e, T_e) in the paper's 4-D layout (comparison layout)."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle)
+
+    @staticmethod
+    def build(axes=None, stream=None):
+        axes = axes if axes is not None else paper_axes4()
+        h = ctypes.c_void_p()
+        check(lib().rc_build_table4d(ctypes.byref(axes), _stream_ptr(stream), ctypes.byref(h)))
+        return Table4D(h.value)
+
+    @staticmethod
+    def from_values(axes, values, stream=None):
+        v = np.ascontiguousarray(values, dtype=np.float32).ravel()
+        if v.size != int(np.prod(list(axes.n))):
+            raise ValueError("values do not match the axes")
+        h = ctypes.c_void_p()
+        check(lib().rc_table4d_import(ctypes.byref(axes), v.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream),
+                                      ctypes.byref(h)))
+        return Table4D(h.value)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RadcoolError(-5, "4-D table destroyed")
+        return self._h
+
+    def export(self):
+        a = Axes4()
+        check(lib().rc_table4d_export(self.handle, ctypes.byref(a), None))
+        v = np.empty(tuple(a.n), dtype=np.float32)
+        check(lib().rc_table4d_export(self.handle, None, v.ctypes.data_as(ctypes.c_void_p)))
+        return a, v
+
+    def destroy(self):
+        if self._h:
+            lib().rc_table4d_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def rates4d(table4d, state, T_floor=1.0e6, stream=None):
+    """(Q_rad, status) tensors from the 4-D table for a dict of device tensors."""
+    import torch
+    n = _check_state(state)
+    dev = state["n_e"].device
+    q = torch.empty(n, dtype=torch.float64, device=dev)
+    st = torch.empty(n, dtype=torch.uint8, device=dev)
+    s = _state(state)
+    check(lib().rc_rates4d(table4d.handle, ctypes.byref(s), n, float(T_floor), q.data_ptr(), st.data_ptr(),
+                           _stream_ptr(stream)))
+    return q, st
+
+
+def selftest_node4d_host(H, B, n_e, T):
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (H, B, n_e, T)]
+    out = np.empty_like(a[0])
+    ptr = lambda v: v.ctypes.data_as(ctypes.c_void_p)
+    check(lib().rc_selftest_node4d_host(*[ptr(v) for v in a], a[0].size, ptr(out)))
+    return out
+
+
+def selftest_rates4d_host(axes, values, cells, T_floor=1.0e6):
+    v = np.ascontiguousarray(values, dtype=np.float32).ravel()
+    a = [np.ascontiguousarray(cells[k], dtype=np.float64) for k in ("n_e", "T_e", "B", "H")]
+    q = np.empty_like(a[0])
+    st = np.empty(a[0].size, dtype=np.uint8)
+    ptr = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    check(lib().rc_selftest_rates4d_host(ctypes.byref(axes), ptr(v), *[ptr(x) for x in a], a[0].size,
+                                         float(T_floor), ptr(q), ptr(st)))
+    return q, st

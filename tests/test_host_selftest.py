@@ -250,3 +250,47 @@ def test_rad_pressure_correction_on_host():
     assert np.array_equal(thick.astype(bool), rthick)
     assert np.max(rel_err(T, ref)) < 1e-14
     assert np.isnan(R.selftest_radp_host(np.array([0.0]), np.array([1e6]), np.array([1e6]))[0][0])
+
+
+def test_node4d_values_match_oracle_on_paper_ranges():
+    """log2 Q_total at 4-D nodes (closed forms combined in log space) against
+    the oracle's linear-space evaluation, over the paper's ranges."""
+    from oracle import table4d as T4
+    ax = T4.paper_axes(12)
+    tab = T4.build(ax)
+    g = np.meshgrid(*[10.0 ** a.nodes() for a in ax], indexing="ij")
+    got = R.selftest_node4d_host(*[x.ravel() for x in g]).reshape(tab.shape)
+    assert np.max(np.abs(got - tab)) < 1e-9
+
+
+def test_rates4d_on_host_match_oracle_interpolation():
+    from oracle import table4d as T4
+    ax = T4.paper_axes(10)
+    tab = T4.build(ax).astype(np.float32)
+    axes = R.Axes4()
+    for d, a in enumerate(ax):
+        axes.n[d], axes.lo[d], axes.hi[d] = a.n, a.lo, a.hi
+    cells = W.workload(0, n=3000)
+    q, st = R.selftest_rates4d_host(axes, tab, cells)
+    ref = T4.q_total(tab.astype(np.float64), ax, cells["n_e"], cells["T_e"], cells["B"], cells["H"])
+    ref = np.where(cells["T_e"] < 1e6, 0.0, ref)
+    assert np.max(rel_err(q, ref)) < 1e-12
+    assert np.all(st == 0)
+
+
+def test_converged_step_may_not_cross_a_table_node():
+    """A cell of the 256^3 iid workload (index 10735542) whose last Newton step,
+    below sqrt(tol), crossed a T_e node of the 128^3 tables: accepted without an
+    evaluation on the far side it left an error first order in the slope jump
+    (T_e' off by ~3e-9).  The step is now evaluated there first."""
+    spec = T.TableSpec.default(128)
+    co, re, st = T.quantize_tables(T.build_tables(spec))
+    resid = np.concatenate([re[k].ravel() for k in T.TABLE_NAMES])
+    coeffs = np.stack([co[k] for k in T.TABLE_NAMES])
+    cell = dict(zip(W.FIELDS, ([3.02408923389808e+19], [308704708752.5737], [1901842603164.162],
+                               [60328704.91455346], [272773157.94663656])))
+    cell = {k: np.array(v) for k, v in cell.items()}
+    got = R.selftest_step_host(R.default_spec(128), resid, coeffs, cell, DT)
+    ref = S.step_be(S.TableSet(spec, st), *[cell[k] for k in W.FIELDS], DT)
+    for k in ("T_e_new", "T_i_new"):
+        assert rel_err(got[k], ref[k])[0] < 1e-12, k
