@@ -10,10 +10,9 @@ Prints one JSON line.
 
 Roofline: algorithmic HBM bytes per step = 72 B per cell (read n_e, T_e, T_i,
 B, H as FP64; write T_e', T_i', Q_rad, Q_cc as FP64) + one read of the four
-tables; the status byte (1 B/cell) is counted too.  A Newton step is one
-rc_cool_step call: a counter reset and the deferral launches (the first over
-all cells, the later ones over the queued stragglers).  Achieved = bytes /
-average step time from HIP events on the launch stream; peak = 8 TB/s.
+tables; the status byte (1 B/cell) is counted too.  A step is one
+rc_cool_step call (one launch).  Achieved = bytes / average step time from
+HIP events on the launch stream; peak = 8 TB/s.
 traffic: HBM bytes per step from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
 scaled by a plain 512 MiB copy's readings, taken from the committed counter
 summary when it was measured on the current kernel sources (else null).
@@ -50,7 +49,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = 5 * 8 + 4 * 8 + 1      # state in, T', Q_rad, Q_cc out, status
 COPY_BYTES = 64 << 23                   # the calibration copy: 512 MiB read and written
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "newton_iid256_t128_counters.md")
-STEP_KERNELS = re.compile(r"k_newton_phase<rc::GlobalTab,|k_zero_counts")   # demangled names, FP32 tables
+STEP_KERNELS = re.compile(r"k_step<0, rc::GlobalTab>")   # the Newton kernel (demangled name), FP32 tables
 
 
 def source_hash():
@@ -83,12 +82,13 @@ def counters_summary(fetch_dir, write_dir):
     copy = [k for k in fetch if "copyBuffer" in k]
     if not copy:
         raise SystemExit("no copy kernel in the FETCH pass: run it with --calibrate-copy")
-    f_copy = np.mean(fetch[copy[0]]) * 1024.0
-    w_copy = np.mean(write[copy[0]]) * 1024.0
+    # the 512 MiB copies are the largest copy dispatches (small uploads use the same kernel)
+    f_copy = max(v for k in copy for v in fetch[k]) * 1024.0
+    w_copy = max(v for k in copy if k in write for v in write[k]) * 1024.0
     f_scale, w_scale = COPY_BYTES / f_copy, COPY_BYTES / w_copy
 
     def per_step(table):
-        first = [k for k in table if "k_newton_phase<rc::GlobalTab, true, false>" in k]
+        first = [k for k in table if STEP_KERNELS.search(k)]
         steps = len(table[first[0]]) if first else 0
         total = sum(sum(v) for k, v in table.items() if STEP_KERNELS.search(k)) * 1024.0
         return total / max(steps, 1), steps
@@ -366,7 +366,7 @@ def main():
     }
     if not args.no_variants:
         var = {}
-        for name, kw, steps in (("newton_plain", dict(block=256), 3),
+        for name, kw, steps in (("newton_block256", dict(block=256), 3),
                                 ("rates_global", dict(scheme="rates"), 5),
                                 ("explicit16_global", dict(scheme="explicit16"), 3),
                                 ("rates_direct", dict(scheme="rates", variant="direct"), 1)):

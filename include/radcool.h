@@ -140,11 +140,9 @@ typedef struct {
   int32_t scheme;        /* RC_SCHEME_*: backward Euler (Newton), 16-substep explicit, or rates only */
   int32_t variant;       /* RC_VARIANT_*: how tables are read; DIRECT evaluates closed forms (no tables) */
   int32_t max_iter;      /* Newton iteration cap (default 60) */
-  int32_t block;         /* 0 = library choice: for the Newton scheme a sequence of
-                            launches that set slow cells aside and finish them on
-                            dense wavefronts (per-call scratch from a library-owned
-                            stream-ordered pool); 64, 128, 192 or 256 = one
-                            launch, one cell per thread, with that workgroup size */
+  int32_t block;         /* threads per workgroup (one cell per thread): 64, 128, 192
+                            or 256; 0 = library choice (64 for the Newton scheme,
+                            256 otherwise) */
   double T_floor;        /* K, cooling is zero below it (Sec. III.B.2; default 1e6) */
   double tol;            /* target relative accuracy of T_e' (default 1e-12): a Newton step
                             below sqrt(tol) in ln T_e' ends the solve */

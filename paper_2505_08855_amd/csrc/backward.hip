@@ -162,7 +162,7 @@ extern "C" rc_status rc_selftest_backward_host(const rc_table_spec* spec, const 
   for (int k = 0; k < 4; ++k)
     for (int j = 0; j < 4; ++j) host.coef[k][j] = coeffs[4 * k + j];
   StepParams P;
-  rc_status st = make_params(&host, dt, opts, &P);
+  rc_status st = make_params(&host, dt, opts, &P, true);
   if (st != RC_OK) return st;
   const bool newton = opts->scheme == RC_SCHEME_NEWTON;
   if (opts->scheme == RC_SCHEME_EXPLICIT16) return set_error(RC_EUNSUPPORTED, "explicit scheme has no adjoint");

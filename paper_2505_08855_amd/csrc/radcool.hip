@@ -163,6 +163,12 @@ std::vector<float> storage_values(const rc_table_spec& s, const float* resid) {
   return v;
 }
 
+void fill_geom(rc_tables_s* t) {
+  fill_axes(t->spec, t->geom.ax);
+  for (int k = 0; k < 4; ++k)
+    for (int j = 0; j < 4; ++j) t->geom.coef[k][j] = t->coef[k][j];
+}
+
 rc_status upload(rc_tables_s* t, void* stream) {
   const int64_t vc = volume(t->spec.cool), vk = volume(t->spec.coul);
   const bool bf = t->spec.value_dtype == RC_VALUE_BF16;
@@ -184,7 +190,12 @@ rc_status upload(rc_tables_s* t, void* stream) {
   }
   if (bf)
     for (int64_t i = 0; i < vk; ++i) packed16[4 * vc + i] = bf16_bits(t->resid[3 * vc + i]);
-  hipError_t e = hipMalloc(&t->d_cool, cool_bytes);
+  fill_geom(t);
+  hipError_t e = hipMalloc(&t->d_geom, sizeof(TableGeom));
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(table geometry)");
+  e = hipMemcpy(t->d_geom, &t->geom, sizeof(TableGeom), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "table geometry upload");
+  e = hipMalloc(&t->d_cool, cool_bytes);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(cooling tables)");
   e = hipMalloc(&t->d_coul, coul_bytes);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(Coulomb table)");
@@ -200,6 +211,7 @@ rc_status upload(rc_tables_s* t, void* stream) {
 
 void destroy_tables(rc_tables_s* t) {
   if (!t) return;
+  if (t->d_geom) (void)hipFree(t->d_geom);
   if (t->d_cool) (void)hipFree(t->d_cool);
   if (t->d_coul) (void)hipFree(t->d_coul);
   if (t->d_counter) (void)hipFree(t->d_counter);
@@ -497,7 +509,7 @@ extern "C" rc_status rc_selftest_step_host(const rc_table_spec* spec, const floa
   for (int k = 0; k < 4; ++k)
     for (int j = 0; j < 4; ++j) host.coef[k][j] = coeffs[4 * k + j];
   StepParams P;
-  rc_status st = make_params(&host, dt, opts, &P);
+  rc_status st = make_params(&host, dt, opts, &P, true);
   if (st != RC_OK) return st;
   const int64_t vc = volume(spec->cool);
   const std::vector<float> stored = storage_values(*spec, resid);

@@ -36,7 +36,7 @@ struct CoulPoint {
 
 template <class Tab>
 RC_HD CoolPoint cool_point(const Tab& tab, const StepParams& P, double u0, double u1, double u2, int n1, int n2) {
-  const Coord c0 = axis_coord(u0, P.ax[0]), c1 = axis_coord(u1, P.ax[1]), c2 = axis_coord(u2, P.ax[2]);
+  const Coord c0 = axis_coord(u0, P.g->ax[0]), c1 = axis_coord(u1, P.g->ax[1]), c2 = axis_coord(u2, P.g->ax[2]);
   CoolPoint r;
   double yb = 0.0, ys = 0.0, ye = 0.0;
   double gb[3] = {0.0, 0.0, 0.0}, gse[3] = {0.0, 0.0, 0.0};
@@ -62,9 +62,9 @@ RC_HD CoolPoint cool_point(const Tab& tab, const StepParams& P, double u0, doubl
     }
   }
   const double f0 = c0.i + c0.t, f1 = c1.i + c1.t, f2 = c2.i + c2.t;
-  const double* cb = P.coef[0];
-  const double* cs = P.coef[1];
-  const double* ce = P.coef[2];
+  const double* cb = P.g->coef[0];
+  const double* cs = P.g->coef[1];
+  const double* ce = P.g->coef[2];
   r.yb = cb[0] + cb[1] * f0 + cb[2] * f1 + cb[3] * f2 + yb;
   r.yse = (cs[0] + ce[0]) + (cs[1] + ce[1]) * f0 + (cs[2] + ce[2]) * f1 + (cs[3] + ce[3]) * f2 + ys + ye;
   const double dfdu[3] = {c0.dfdu, c1.dfdu, c2.dfdu};
@@ -77,7 +77,7 @@ RC_HD CoolPoint cool_point(const Tab& tab, const StepParams& P, double u0, doubl
 
 template <class Tab>
 RC_HD CoulPoint coul_point(const Tab& tab, const StepParams& P, double u0, double u1, double u2, int n1, int n2) {
-  const Coord c0 = axis_coord(u0, P.ax[3]), c1 = axis_coord(u1, P.ax[4]), c2 = axis_coord(u2, P.ax[5]);
+  const Coord c0 = axis_coord(u0, P.g->ax[3]), c1 = axis_coord(u1, P.g->ax[4]), c2 = axis_coord(u2, P.g->ax[5]);
   CoulPoint r;
   double y = 0.0, g[3] = {0.0, 0.0, 0.0};
   int k = 0;
@@ -96,7 +96,7 @@ RC_HD CoulPoint coul_point(const Tab& tab, const StepParams& P, double u0, doubl
       }
     }
   }
-  const double* co = P.coef[3];
+  const double* co = P.g->coef[3];
   r.y = co[0] + co[1] * (c0.i + c0.t) + co[2] * (c1.i + c1.t) + co[3] * (c2.i + c2.t) + y;
   const double dfdu[3] = {c0.dfdu, c1.dfdu, c2.dfdu};
   for (int q = 0; q < 3; ++q) r.dy[q] = (co[q + 1] + g[q]) * dfdu[q];

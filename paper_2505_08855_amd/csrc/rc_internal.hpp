@@ -25,6 +25,8 @@ struct rc_tables_s {
   // float per Coulomb node; bfloat16 form uint2 (4 x bf16) and uint16
   void* d_cool = nullptr;
   void* d_coul = nullptr;
+  rc::TableGeom geom{};             // axes and affine coefficients (host copy)
+  rc::TableGeom* d_geom = nullptr;  // the same in device memory, read by the kernels
   void* d_counter = nullptr;        // work-queue counter of the batched kernel (allocated on first use)
   void* d_gscratch = nullptr;       // backward: synch * eta table-gradient accumulator (first use)
 };
@@ -37,7 +39,11 @@ bool handle_ok(rc_tables t);
 bool spec_ok(const rc_table_spec* s);
 int64_t volume(const rc_axes& a);
 void fill_axes(const rc_table_spec& s, AxisP ax[6]);
-rc_status make_params(rc_tables t, double dt, const rc_step_opts* o, StepParams* P);
+// fill t->geom from t->spec and t->coef
+void fill_geom(rc_tables_s* t);
+// Validate the options and fill P; P->g points to the device copy of the table
+// geometry, or with host = true (host self-tests) to the host copy.
+rc_status make_params(rc_tables t, double dt, const rc_step_opts* o, StepParams* P, bool host = false);
 // host copy of residuals in their storage form (bfloat16-rounded for that form)
 std::vector<float> storage_values(const rc_table_spec& s, const float* resid);
 

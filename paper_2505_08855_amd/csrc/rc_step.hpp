@@ -59,10 +59,17 @@ struct AxisP {
   int n;
 };
 
-// Everything a step kernel needs besides the table memory.
-struct StepParams {
+// Geometry of a table set: fixed per table handle, kept in device memory (a
+// host copy serves the host self-tests) so that kernels read it through the
+// scalar cache instead of holding it in registers.
+struct TableGeom {
   AxisP ax[6];          // cooling (N, T_e, B), Coulomb (n_e, T_e, T_i)
   double coef[4][4];    // affine part of each log2 table in node-index space
+};
+
+// Everything a step kernel needs besides the table memory.
+struct StepParams {
+  const TableGeom* g;
   double dt, T_floor, tol, ln_lambda;
   double ln_T_floor, sqrt_tol;   // log(T_floor), sqrt(tol)
   int max_iter, scheme;
@@ -173,17 +180,17 @@ struct CellSolver {
     invH = 1.0 / h;
     invH2 = invH * invH;
     const double lne = flog10(n_e);
-    const Coord cN = axis_coord(lne + flog10(h), P.ax[0]);
-    const Coord cB = axis_coord(flog10(b), P.ax[2]);
-    const Coord cn = axis_coord(lne, P.ax[3]);
+    const Coord cN = axis_coord(lne + flog10(h), P.g->ax[0]);
+    const Coord cB = axis_coord(flog10(b), P.g->ax[2]);
+    const Coord cn = axis_coord(lne, P.g->ax[3]);
     iN = cN.i; tN = cN.t;
     iB = cB.i; tB = cB.t;
     in_ = cn.i; tn = cn.t;
     const double s0 = flog(te);
     const double lte = s0 * (1.0 / kLn10);
     clamp = cool_off ? ST_GAS_FLOOR : 0;
-    if (cN.clamped || cB.clamped || axis_coord(lte, P.ax[1]).clamped) clamp |= ST_CLAMP_COOL;
-    if (cn.clamped || axis_coord(lte, P.ax[4]).clamped || axis_coord(flog10(ti), P.ax[5]).clamped)
+    if (cN.clamped || cB.clamped || axis_coord(lte, P.g->ax[1]).clamped) clamp |= ST_CLAMP_COOL;
+    if (cn.clamped || axis_coord(lte, P.g->ax[4]).clamped || axis_coord(flog10(ti), P.g->ax[5]).clamped)
       clamp |= ST_CLAMP_COUL;
     iT = ie = ii = -1;
     return s0;
@@ -209,9 +216,9 @@ struct CellSolver {
       }
     }
     const double fN = iN + tN, fB = iB + tB;
-    const double* cb = P.coef[0];
-    const double* cs = P.coef[1];
-    const double* ce = P.coef[2];
+    const double* cb = P.g->coef[0];
+    const double* cs = P.g->coef[1];
+    const double* ce = P.g->coef[2];
     Ab = cb[0] + cb[1] * fN + cb[2] * (double)i + cb[3] * fB + lb;
     Sb = cb[2] + hb - lb;
     Ase = (cs[0] + ce[0]) + (cs[1] + ce[1]) * fN + (cs[2] + ce[2]) * (double)i + (cs[3] + ce[3]) * fB + lse;
@@ -226,7 +233,7 @@ struct CellSolver {
     v10 = w0 * tab.coul_at(in_, je + 1, ji) + w1 * tab.coul_at(in_ + 1, je + 1, ji);
     v01 = w0 * tab.coul_at(in_, je, ji + 1) + w1 * tab.coul_at(in_ + 1, je, ji + 1);
     v11 = w0 * tab.coul_at(in_, je + 1, ji + 1) + w1 * tab.coul_at(in_ + 1, je + 1, ji + 1);
-    const double* co = P.coef[3];
+    const double* co = P.g->coef[3];
     K0 = co[0] + co[1] * (in_ + tn) + co[2] * (double)je + co[3] * (double)ji;
   }
 
@@ -266,7 +273,7 @@ struct CellSolver {
   // gathered) and the partial derivatives d ln v_c / d ln T_e, d ln v_c / d ln T_i
   RC_HD double kcoul_at(const Coord& ce, const Coord& ci, double* dlx, double* dlz) const {
     const double te = ce.t, ti = ci.t;
-    const double c2 = P.coef[3][2], c3 = P.coef[3][3];
+    const double c2 = P.g->coef[3][2], c3 = P.g->coef[3][3];
     const double y = K0 + c2 * te + c3 * ti + (1.0 - te) * (1.0 - ti) * v00 + te * (1.0 - ti) * v10 +
                      (1.0 - te) * ti * v01 + te * ti * v11;
     const double dye = c2 + (1.0 - ti) * (v10 - v00) + ti * (v11 - v01);
@@ -278,7 +285,7 @@ struct CellSolver {
 
   // the same at T_i = z, gathering the Coulomb cell if z left the cached one
   RC_HD double kcoul(const Coord& ce, double z, double* dlx, double* dlz) {
-    const Coord ci = axis_coord(flog10(z), P.ax[5]);
+    const Coord ci = axis_coord(flog10(z), P.g->ax[5]);
     if (ce.i != ie || ci.i != ii) load_coul(ce.i, ci.i);
     return kcoul_at(ce, ci, dlx, dlz);
   }
@@ -336,10 +343,10 @@ struct CellSolver {
                      double* K_first, double* dzdx_out, double* ds3) {
     const double lx = s * (1.0 / kLn10);
     double q, dq, dzdx;
-    const Coord cT = axis_coord(lx, P.ax[1]);
-    const Coord ce = axis_coord(lx, P.ax[4]);
+    const Coord cT = axis_coord(lx, P.g->ax[1]);
+    const Coord ce = axis_coord(lx, P.g->ax[4]);
     const double z0 = fmin(fmax(*z, fmin(x, T_i)), fmax(x, T_i));
-    const Coord ci = axis_coord(flog10(z0), P.ax[5]);
+    const Coord ci = axis_coord(flog10(z0), P.g->ax[5]);
     gather(cT, ce, ci, on);
     q_rad(x, cT, on, &q, &dq);
     *z = solve_z(x, ce, z0, ci, &dzdx, K_first);
@@ -362,8 +369,7 @@ struct CellSolver {
   // Newton driver.  Every evaluation of the outer residual goes through one
   // call site (newton_round: evaluate at the pending point, then choose the
   // next one), so the inlined rate code exists once in the kernel; the whole
-  // iteration state lives in NewtonState so that a kernel can also set a cell
-  // aside between rounds and resume it in a later launch (straggler deferral).
+  // iteration state lives in NewtonState, separate from the cell's constants.
   enum { FIRST = 0, ITER = 1, PROBE_ON = 2, PROBE_OFF = 3, FINAL = 4 };
   enum { F_LO_KNOWN = 1, F_FLOOR_PENDING = 2, F_HEATING = 4, F_ON = 8 };
 
@@ -485,8 +491,8 @@ struct CellSolver {
         const double xn = fexp(sn);
         const double zn = ns.z + dzdx * (xn - ns.xe);
         const double lxn = sn * (1.0 / kLn10);
-        const bool same_cells = (!(ns.flags & F_ON) || axis_coord(lxn, P.ax[1]).i == iT) &&
-                                axis_coord(lxn, P.ax[4]).i == ie && axis_coord(flog10(zn), P.ax[5]).i == ii;
+        const bool same_cells = (!(ns.flags & F_ON) || axis_coord(lxn, P.g->ax[1]).i == iT) &&
+                                axis_coord(lxn, P.g->ax[4]).i == ie && axis_coord(flog10(zn), P.g->ax[5]).i == ii;
         if (same_cells) {
           ns.z = zn;
           ns.kind = FINAL; ns.se = sn; ns.xe = xn; ns.flags &= ~F_ON;
@@ -525,9 +531,9 @@ struct CellSolver {
     for (int k = 0; k < 16; ++k) {
       double q, dq, dlx, dlz;
       const bool on = te >= Tf();
-      const Coord cT = axis_coord(lte, P.ax[1]);
-      const Coord ce = axis_coord(lte, P.ax[4]);
-      const Coord ci = axis_coord(flog10(ti), P.ax[5]);
+      const Coord cT = axis_coord(lte, P.g->ax[1]);
+      const Coord ce = axis_coord(lte, P.g->ax[4]);
+      const Coord ci = axis_coord(flog10(ti), P.g->ax[5]);
       gather(cT, ce, ci, on);
       q_rad(te, cT, on, &q, &dq);
       const double K = kcoul_at(ce, ci, &dlx, &dlz);
@@ -548,9 +554,9 @@ struct CellSolver {
     const double lte = s0 * (1.0 / kLn10);
     double q, dq, dlx, dlz;
     const bool on = T_e >= Tf();
-    const Coord cT = axis_coord(lte, P.ax[1]);
-    const Coord ce = axis_coord(lte, P.ax[4]);
-    const Coord ci = axis_coord(flog10(T_i), P.ax[5]);
+    const Coord cT = axis_coord(lte, P.g->ax[1]);
+    const Coord ce = axis_coord(lte, P.g->ax[4]);
+    const Coord ci = axis_coord(flog10(T_i), P.g->ax[5]);
     gather(cT, ce, ci, on);
     q_rad(T_e, cT, on, &q, &dq);
     o->q_rad = q;
@@ -561,7 +567,7 @@ struct CellSolver {
 
   // the three cooling quantities separately at the input state (diagnostic outputs)
   RC_HD void diagnostics(double s0, CellOut* o) {
-    const Coord cT = axis_coord(s0 * (1.0 / kLn10), P.ax[1]);
+    const Coord cT = axis_coord(s0 * (1.0 / kLn10), P.g->ax[1]);
     const double wN[2] = {1.0 - tN, tN};
     const double wB[2] = {1.0 - tB, tB};
     const double wT[2] = {1.0 - cT.t, cT.t};
@@ -581,7 +587,7 @@ struct CellSolver {
     const double fN = iN + tN, fT = cT.i + cT.t, fB = iB + tB;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const double* co = P.coef[k];
+      const double* co = P.g->coef[k];
       y[k] += co[0] + co[1] * fN + co[2] * fT + co[3] * fB;
     }
     o->q_brem = fexp2(y[0]) * invH2;

@@ -5,13 +5,10 @@
 // outputs are written once, coalesced.
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
 #include <cmath>
 #include <cstdint>
-#include <mutex>
 
 #include "radcool.h"
-#include "rc_defer.hpp"
 #include "rc_internal.hpp"
 #include "rc_kernels.hpp"
 
@@ -36,28 +33,6 @@ __global__ __launch_bounds__(256, kStepWaves<SCHEME>) void k_step(Tab tab, StepP
   store(o, i, r);
 }
 
-// One launch of the Newton solve with straggler deferral: FRESH takes the
-// cells themselves (one per thread), later launches the previous launch's
-// queue (grid-stride over 64-entry chunks); LAST runs everything to completion.
-template <class Tab, bool FRESH, bool LAST>
-__global__ __launch_bounds__(256, RC_NEWTON_WAVES) void k_newton_phase(Tab tab, StepParams P, StateArgs s, OutArgs o,
-                                                                      int64_t n, PhaseArgs q) {
-  const bool diag = o.Q_brem || o.Q_syn || o.eta;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  int64_t items = n;
-  if (!FRESH) {
-    const unsigned long long c = q.count[q.phase - 1];
-    items = c < (unsigned long long)q.in.cap ? (int64_t)c : q.in.cap;
-  }
-  for (int64_t chunk = wave; chunk * 64 < items; chunk += waves)
-    newton_phase_chunk<Tab, FRESH, LAST>(tab, P, s, o, q, items, chunk, diag);
-}
-
-__global__ void k_zero_counts(unsigned long long* c, int k) {
-  if ((int)threadIdx.x < k) c[threadIdx.x] = 0;
-}
-
 __global__ __launch_bounds__(256) void k_direct(StepParams P, StateArgs s, OutArgs o, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -66,7 +41,7 @@ __global__ __launch_bounds__(256) void k_direct(StepParams P, StateArgs s, OutAr
   store(o, i, r);
 }
 
-rc_status make_params(rc_tables t, double dt, const rc_step_opts* o, StepParams* P) {
+rc_status make_params(rc_tables t, double dt, const rc_step_opts* o, StepParams* P, bool host) {
   if (!o) return set_error(RC_EINVAL, "step options are NULL");
   if (o->scheme < RC_SCHEME_NEWTON || o->scheme > RC_SCHEME_RATES) return set_error(RC_EINVAL, "unknown scheme");
   if (o->variant < RC_VARIANT_AUTO || o->variant > RC_VARIANT_DIRECT) return set_error(RC_EINVAL, "unknown variant");
@@ -76,9 +51,13 @@ rc_status make_params(rc_tables t, double dt, const rc_step_opts* o, StepParams*
   if (o->block != 0 && (o->block < 64 || o->block > 256 || (o->block % 64) != 0))
     return set_error(RC_EINVAL, "block must be 0 or a multiple of 64 in [64, 256]");
   if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(RC_EINVAL, "dt must be finite and > 0");
-  fill_axes(t->spec, P->ax);
-  for (int k = 0; k < 4; ++k)
-    for (int j = 0; j < 4; ++j) P->coef[k][j] = t->coef[k][j];
+  if (host) {
+    fill_geom(t);
+    P->g = &t->geom;
+  } else {
+    if (!t->d_geom) return set_error(RC_ESTATE, "table geometry is not on the device");
+    P->g = t->d_geom;
+  }
   P->dt = dt;
   P->T_floor = o->T_floor;
   P->tol = o->tol;
@@ -90,97 +69,6 @@ rc_status make_params(rc_tables t, double dt, const rc_step_opts* o, StepParams*
   return RC_OK;
 }
 
-namespace {
-
-constexpr int kMaxDevices = 64;
-
-// Per-call scratch comes from a library-owned stream-ordered pool per device
-// (created on first use); freed blocks stay reserved for the next call, so
-// repeated calls do not return to the driver, and calls on different streams
-// never share scratch.
-hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t hs) {
-  static std::mutex mu;
-  static hipMemPool_t pools[kMaxDevices] = {};
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-  {
-    std::lock_guard<std::mutex> lock(mu);
-    if (!pools[dev]) {
-      hipMemPoolProps props = {};
-      props.allocType = hipMemAllocationTypePinned;
-      props.handleTypes = hipMemHandleTypeNone;
-      props.location.type = hipMemLocationTypeDevice;
-      props.location.id = dev;
-      e = hipMemPoolCreate(&pools[dev], &props);
-      if (e != hipSuccess) return e;
-      uint64_t keep = UINT64_MAX;
-      e = hipMemPoolSetAttribute(pools[dev], hipMemPoolAttrReleaseThreshold, &keep);
-      if (e != hipSuccess) return e;
-    }
-  }
-  return hipMallocFromPoolAsync(p, bytes, pools[dev], hs);
-}
-
-size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
-
-DeferQueue queue_at(char* base, int64_t cap) {
-  DeferQueue q;
-  q.cap = cap;
-  q.cell = (int64_t*)base;
-  q.v = (double*)(base + align256(sizeof(int64_t) * cap));
-  q.packed = (unsigned*)(base + align256(sizeof(int64_t) * cap) + align256(sizeof(double) * kQueueDoubles * cap));
-  return q;
-}
-
-size_t queue_bytes(int64_t cap) {
-  return align256(sizeof(int64_t) * cap) + align256(sizeof(double) * kQueueDoubles * cap) +
-         align256(sizeof(unsigned) * cap);
-}
-
-int device_cus() {
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 256;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
-  return cus;
-}
-
-// The Newton solve over n >= 1 cells as kPhases launches with deferral queues
-// in per-call scratch (two queues used alternately, plus the counters).
-template <class Tab>
-rc_status launch_newton_phased(const Tab& tab, const StepParams& P, const StateArgs& s, const OutArgs& o, int64_t n,
-                               hipStream_t hs) {
-  const int64_t cap = defer_capacity(n);
-  const size_t qb = queue_bytes(cap);
-  void* scratch = nullptr;
-  hipError_t e = scratch_alloc(&scratch, 256 + 2 * qb, hs);
-  if (e != hipSuccess) return hip_fail(e, "rc_cool_step: scratch allocation");
-  char* base = (char*)scratch;
-  unsigned long long* count = (unsigned long long*)base;
-  const DeferQueue qs[2] = {queue_at(base + 256, cap), queue_at(base + 256 + qb, cap)};
-  hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, hs, count, kPhases);
-  const unsigned fresh_grid = (unsigned)((n + 255) / 256);
-  const int64_t later = std::min<int64_t>((cap + 255) / 256, (int64_t)device_cus() * 8);
-  for (int p = 0; p < kPhases; ++p) {
-    const PhaseArgs a{qs[(p + 1) % 2], qs[p % 2], count, p};
-    if (p == 0)
-      hipLaunchKernelGGL((k_newton_phase<Tab, true, false>), dim3(fresh_grid), dim3(256), 0, hs, tab, P, s, o, n, a);
-    else if (p < kPhases - 1)
-      hipLaunchKernelGGL((k_newton_phase<Tab, false, false>), dim3((unsigned)later), dim3(256), 0, hs, tab, P, s, o,
-                         n, a);
-    else
-      hipLaunchKernelGGL((k_newton_phase<Tab, false, true>), dim3((unsigned)later), dim3(256), 0, hs, tab, P, s, o,
-                         n, a);
-  }
-  e = hipGetLastError();
-  const hipError_t fe = hipFreeAsync(scratch, hs);
-  if (e != hipSuccess) return hip_fail(e, "rc_cool_step launch");
-  if (fe != hipSuccess) return hip_fail(fe, "rc_cool_step: scratch release");
-  return RC_OK;
-}
-
-}  // namespace
 
 }  // namespace rc
 
@@ -210,15 +98,16 @@ extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n,
     return set_error(RC_ESTATE, "rc_cool_step: tables live on another device than the current one");
   StateArgs s{state->n_e, state->T_e, state->T_i, state->B, state->H, state->T_floor_gas};
   OutArgs o{out->T_e_new, out->T_i_new, out->Q_rad, out->Q_cc, out->Q_brem, out->Q_syn, out->eta, out->status};
-  const int block = opts->block ? opts->block : 256;
+  // library choice: one-wavefront workgroups for the Newton solve (measured
+  // fastest: a workgroup retires as soon as its slowest cell is done), 256
+  // threads for the single-evaluation schemes
+  const int block = opts->block ? opts->block : (opts->scheme == RC_SCHEME_NEWTON ? 64 : 256);
   const int64_t grid = (n + block - 1) / block;
   if (grid > 0x7fffffffLL) return set_error(RC_EINVAL, "rc_cool_step: n too large for one launch");
   hipStream_t hs = (hipStream_t)stream;
   // the same launches for every table accessor
   const auto launch = [&](auto tab) -> rc_status {
       using Tab = decltype(tab);
-      if (opts->scheme == RC_SCHEME_NEWTON && opts->block == 0)
-        return launch_newton_phased(tab, P, s, o, n, hs);
       if (opts->scheme == RC_SCHEME_NEWTON)
         hipLaunchKernelGGL((k_step<SCHEME_NEWTON, Tab>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, n);
       else if (opts->scheme == RC_SCHEME_EXPLICIT16)

@@ -282,14 +282,11 @@ def test_full_size_iid256_sampled(dev, oracle128):
 
 @pytest.mark.parametrize("n,dt_scale", [(100_003, 1.0), (100_003, 1e3), (1, 1.0), (63, 1e3), (65, 1e3),
                                          (4099, 1e3)])
-def test_deferred_newton_equals_plain_kernel(dev, imported64, n, dt_scale):
-    """The default Newton launch sets stragglers aside in a queue and resumes
-    them in later launches (straggler deferral); a plain one-cell-per-thread
-    launch (explicit block size) runs the same per-cell steps.  Multiply-adds
-    may be fused differently in the two kernels, so values agree to rounding;
-    a state resumed for the wrong cell would show up as a gross mismatch.
-    The stiff step (dt x 1e3) defers most cells, several launches deep; the
-    ragged sizes leave partial waves in every launch."""
+def test_newton_launch_shapes_agree(dev, imported64, n, dt_scale):
+    """The default launch (64-thread workgroups) and 256-thread workgroups run
+    the same per-cell steps; multiply-adds may be fused differently in the two
+    builds, so values agree to rounding.  Ragged sizes leave partial
+    workgroups; the stiff step (dt x 1e3) runs long Newton iterations."""
     gt, _ = imported64
     cells = W.workload(3, n=n)
     st = to_dev(cells, dev)
