@@ -369,7 +369,9 @@ def main():
         for name, kw, steps in (("newton_block256", dict(block=256), 3),
                                 ("rates_global", dict(scheme="rates"), 5),
                                 ("explicit16_global", dict(scheme="explicit16"), 3),
-                                ("rates_direct", dict(scheme="rates", variant="direct"), 1)):
+                                ("rates_direct", dict(scheme="rates", variant="direct"), 1),
+                                ("newton_lds", dict(variant="lds"), 3),
+                                ("rates_lds", dict(scheme="rates", variant="lds"), 5)):
             o = R.default_opts(**kw)
             try:
                 vms, _ = time_steps(R, torch, tables, state, dt, o, out, steps, 1)

@@ -129,8 +129,14 @@ typedef struct {
 enum { RC_SCHEME_NEWTON = 0, RC_SCHEME_EXPLICIT16 = 1, RC_SCHEME_RATES = 2 };
 
 /* How the tables are read.  GLOBAL (what AUTO selects) gathers the corners
- * with plain global loads, through the vector L1 and L2 caches.  LDS is not
- * available in this build (RC_EUNSUPPORTED).  TEX names the texture-memory path
+ * with plain global loads, through the vector L1 and L2 caches.  LDS stages,
+ * per workgroup, the box of table nodes its cells can reach (their N and B
+ * cells of the cooling tables over the whole T_e axis, their n_e cells of the
+ * Coulomb table over the whole T_e x T_i plane) in 256 bytes of LDS per
+ * workgroup thread (64 KiB at 256) when it fits,
+ * and reads the tables from there; a box that does not fit is read from global
+ * memory.  Results equal GLOBAL's.  Its workgroup is opts.block threads (0 =
+ * 256).  It pays only for spatially coherent cell order.  TEX names the texture-memory path
  * of the paper's GPU (Sec. III.A); gfx950 exposes no texture sampling to HIP,
  * so it returns RC_EUNSUPPORTED.  DIRECT evaluates the closed forms of
  * Sec. II per cell instead of tables (rates scheme only). */

@@ -21,6 +21,7 @@
 // monotonically onto it.
 #pragma once
 
+#include "rc_fastmath.hpp"
 #include "rc_physics.hpp"
 
 namespace rc {
@@ -40,21 +41,25 @@ RC_HD double floor_gas_temperature(double r, double a, double h_floor) {
   return 0.5 * kPi * v * v * kMP * kC * kC / kKB;
 }
 
-// T solving a T^4 + n_e k T = n_e k T_e (T <= T_e)
+// T solving a T^4 + n_e k T = n_e k T_e (T <= T_e).  Stops at the root (f no
+// longer positive), or when a step no longer changes s (it is below half an
+// ulp of s), or after a step below 1e-15 relative.
 RC_HD double rad_pressure_temperature(double n_e, double T_e) {
   const double nk = n_e * kKB;
   const double rhs = nk * T_e;
-  double s = fmin(log(T_e), 0.25 * log(rhs / kARad));
+  double s = fmin(flog(T_e), 0.25 * flog(rhs / kARad));
   for (int it = 0; it < 100; ++it) {
-    const double t = exp(s);
+    const double t = fexp(s);
     const double t4 = kARad * t * t * t * t;
     const double f = t4 + nk * t - rhs;
     if (!(f > 0.0)) break;                       // at (or, by rounding, just below) the root
     const double ds = f / (4.0 * t4 + nk * t);
-    s -= ds;
-    if (ds <= 1e-15) break;
+    const double sn = s - ds;
+    if (sn == s) break;
+    s = sn;
+    if (ds <= 1e-15 * fabs(s)) break;
   }
-  return exp(s);
+  return fexp(s);
 }
 
 }  // namespace rc

@@ -141,6 +141,17 @@ struct NewtonState {
   int kind, iters, flags;
 };
 
+// the table coordinates that stay fixed during a cell's solve: N and B of the
+// cooling tables, n_e of the Coulomb table
+struct FixedCoords {
+  Coord N, B, n;
+};
+
+RC_HD FixedCoords fixed_coords(const StepParams& P, double n_e, double b, double h) {
+  const double lne = flog10(n_e);
+  return {axis_coord(lne + flog10(h), P.g->ax[0]), axis_coord(flog10(b), P.g->ax[2]), axis_coord(lne, P.g->ax[3])};
+}
+
 template <class Tab>
 struct CellSolver {
   const Tab& tab;
@@ -179,10 +190,8 @@ struct CellSolver {
     tau_sca = 2.0 * n_e * kSigmaT * h;
     invH = 1.0 / h;
     invH2 = invH * invH;
-    const double lne = flog10(n_e);
-    const Coord cN = axis_coord(lne + flog10(h), P.g->ax[0]);
-    const Coord cB = axis_coord(flog10(b), P.g->ax[2]);
-    const Coord cn = axis_coord(lne, P.g->ax[3]);
+    const FixedCoords f = fixed_coords(P, n_e, b, h);
+    const Coord &cN = f.N, &cB = f.B, &cn = f.n;
     iN = cN.i; tN = cN.t;
     iB = cB.i; tB = cB.t;
     in_ = cn.i; tn = cn.t;

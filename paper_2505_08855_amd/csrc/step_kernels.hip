@@ -5,12 +5,14 @@
 // outputs are written once, coalesced.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdint>
 
 #include "radcool.h"
 #include "rc_internal.hpp"
 #include "rc_kernels.hpp"
+#include "rc_lds.hpp"
 
 namespace rc {
 
@@ -30,6 +32,84 @@ __global__ __launch_bounds__(256, kStepWaves<SCHEME>) void k_step(Tab tab, StepP
   CellOut r;
   const bool diag = o.Q_brem || o.Q_syn || o.eta;
   cool_cell<SCHEME>(tab, P, P.dt, s.n_e[i], s.T_e[i], s.T_i[i], s.B[i], s.H[i], floor_gas_at(s, i), diag, &r);
+  store(o, i, r);
+}
+
+// LDS-tiled variant: the fixed table coordinates of every cell, a workgroup
+// reduction of their range, staging of the box into LDS, then the scheme
+// (every thread of the workgroup reaches both barriers).
+// LDS per workgroup: 256 bytes per cell (64 KiB at 256 cells), so that
+// residency is set by registers, not LDS, at every workgroup size
+constexpr int kLdsPerCell = 256;
+
+template <int SCHEME, class Base>
+__global__ __launch_bounds__(256, kStepWaves<SCHEME>) void k_step_lds(Base base, StepParams P, StateArgs s, OutArgs o,
+                                                                     int64_t n) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ LdsBox box;
+  const int tid = (int)threadIdx.x;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + tid;
+  if (tid < 3) {
+    box.lo[tid] = INT_MAX;
+    box.hi[tid] = INT_MIN;
+  }
+  __syncthreads();
+  if (i < n) {
+    const double n_e = s.n_e[i], B = s.B[i], H = s.H[i];
+    // invalid cells read no table
+    if (!(bad_input(n_e) || bad_input(s.T_e[i]) || bad_input(s.T_i[i]) || bad_input(B) || bad_input(H))) {
+      const FixedCoords f = fixed_coords(P, n_e, B, H);
+      atomicMin(&box.lo[0], f.N.i); atomicMax(&box.hi[0], f.N.i);
+      atomicMin(&box.lo[1], f.B.i); atomicMax(&box.hi[1], f.B.i);
+      atomicMin(&box.lo[2], f.n.i); atomicMax(&box.hi[2], f.n.i);
+    }
+  }
+  __syncthreads();
+  // the box is uniform over the workgroup: keep it in scalar registers; its
+  // extent is the cells' index range plus the upper corner of the highest cell
+  const int c1 = base.c1, k1 = base.k1, k2 = base.k2;
+  const long budget = (long)kLdsPerCell * blockDim.x;
+  int lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = __builtin_amdgcn_readfirstlane(box.lo[d]);
+    hi[d] = __builtin_amdgcn_readfirstlane(box.hi[d]);
+  }
+  int dN = 0, dB = 0, dn = 0;
+  if (hi[0] >= lo[0]) {
+    dN = hi[0] - lo[0] + 2;
+    dB = hi[1] - lo[1] + 2;
+    if ((long)dN * c1 * dB * (long)sizeof(float4) > budget) dN = dB = 0;
+    dn = hi[2] - lo[2] + 2;
+    // the Coulomb box is staged only beside a staged cooling box
+    if (dN == 0 || (long)dN * c1 * dB * (long)sizeof(float4) + (long)dn * k1 * k2 * (long)sizeof(float) > budget)
+      dn = 0;
+  }
+  float4* cool_l = (float4*)lds;
+  float* coul_l = (float*)(lds + (size_t)dN * c1 * dB * sizeof(float4));
+  const int vcool = dN * c1 * dB;
+  for (int k = tid; k < vcool; k += (int)blockDim.x) {
+    const int b = k % dB, t = (k / dB) % c1, a = k / (dB * c1);
+    cool_l[k] = base.cool_at(lo[0] + a, t, lo[1] + b);
+  }
+  const int vcoul = dn * k1 * k2;
+  for (int k = tid; k < vcoul; k += (int)blockDim.x) {
+    const int c = k % k2, t = (k / k2) % k1, a = k / (k2 * k1);
+    coul_l[k] = base.coul_at(lo[2] + a, t, c);
+  }
+  __syncthreads();
+  if (i >= n) return;
+  CellOut r;
+  const bool diag = o.Q_brem || o.Q_syn || o.eta;
+  const double n_e = s.n_e[i], T_e = s.T_e[i], T_i = s.T_i[i], B = s.B[i], H = s.H[i], fg = floor_gas_at(s, i);
+  if (dN == 0) {
+    cool_cell<SCHEME>(base, P, P.dt, n_e, T_e, T_i, B, H, fg, diag, &r);
+  } else if (dn == 0) {
+    const LdsTab<Base, false> tab{base, cool_l, coul_l, lo[0], lo[1], dB, lo[2]};
+    cool_cell<SCHEME>(tab, P, P.dt, n_e, T_e, T_i, B, H, fg, diag, &r);
+  } else {
+    const LdsTab<Base, true> tab{base, cool_l, coul_l, lo[0], lo[1], dB, lo[2]};
+    cool_cell<SCHEME>(tab, P, P.dt, n_e, T_e, T_i, B, H, fg, diag, &r);
+  }
   store(o, i, r);
 }
 
@@ -87,8 +167,6 @@ extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n,
   int variant = opts->variant == RC_VARIANT_AUTO ? RC_VARIANT_GLOBAL : opts->variant;
   if (variant == RC_VARIANT_DIRECT && opts->scheme != RC_SCHEME_RATES)
     return set_error(RC_EUNSUPPORTED, "rc_cool_step: the DIRECT variant evaluates rates only (scheme RC_SCHEME_RATES)");
-  if (variant == RC_VARIANT_LDS)
-    return set_error(RC_EUNSUPPORTED, "rc_cool_step: variant not available in this build");
   if (variant == RC_VARIANT_TEX)
     return set_error(RC_EUNSUPPORTED, "rc_cool_step: gfx950 exposes no texture sampling to HIP; plain global "
                                       "loads already go through the vector L1 cache (use RC_VARIANT_GLOBAL)");
@@ -118,6 +196,21 @@ extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n,
   };
   if (variant == RC_VARIANT_DIRECT) {
     hipLaunchKernelGGL(k_direct, dim3((unsigned)grid), dim3(block), 0, hs, P, s, o, n);
+  } else if (variant == RC_VARIANT_LDS) {
+    // workgroups of 256 cells (or opts.block) share one staged box
+    const int lb = opts->block ? opts->block : 256;
+    const unsigned lg = (unsigned)((n + lb - 1) / lb);
+    st = with_tab(t, [&](auto base) -> rc_status {
+      using Base = decltype(base);
+      if (opts->scheme == RC_SCHEME_NEWTON)
+        hipLaunchKernelGGL((k_step_lds<SCHEME_NEWTON, Base>), dim3(lg), dim3(lb), (size_t)kLdsPerCell * lb, hs, base, P, s, o, n);
+      else if (opts->scheme == RC_SCHEME_EXPLICIT16)
+        hipLaunchKernelGGL((k_step_lds<SCHEME_EXPLICIT16, Base>), dim3(lg), dim3(lb), (size_t)kLdsPerCell * lb, hs, base, P, s, o, n);
+      else
+        hipLaunchKernelGGL((k_step_lds<SCHEME_RATES, Base>), dim3(lg), dim3(lb), (size_t)kLdsPerCell * lb, hs, base, P, s, o, n);
+      return RC_OK;
+    });
+    if (st != RC_OK) return st;
   } else {
     st = with_tab(t, launch);
     if (st != RC_OK) return st;
