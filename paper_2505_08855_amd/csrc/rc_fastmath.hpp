@@ -32,6 +32,25 @@ constexpr double kInvLn10 = 0x1.bcb7b1526e50ep-2;   // 1 / ln 10
 constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;  // sqrt(1/2)
 
 // ln x for finite x > 0
+// single-precision 2^y and log2 x for step proposals that need no more than
+// a few digits: the hardware instructions on the device, the C library on
+// the host
+RC_HD float fexp2_sp(float y) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_exp2f(y);
+#else
+  return exp2f(y);
+#endif
+}
+
+RC_HD float flog2_sp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_logf(x);
+#else
+  return log2f(x);
+#endif
+}
+
 RC_HD double flog(double x) {
   int e;
   double m = frexp(x, &e);           // [1/2, 1)

@@ -339,16 +339,21 @@ struct CellSolver {
 
   // Outer residual G = log1p([c (x - T_e) + c (z - T_i) + dt Q_rad(x)] / (c (T_e + T_i)))
   // at x = exp(s), with its slope dG/ds, Q_rad(x), v_c at the warm start and
-  // dz/dx.  With want3, *ds3 receives the Newton step of the log-log form
-  //   G3 = ln(dt Q_rad(x)) - ln R,   R = c (T_e - x) + c (T_i - z),
-  // which has the sign of G wherever R > 0, provided that form is well
-  // conditioned here: |d ln R / ds| = c x (1 + dz/dx) / R <= 2 (near x = T_e,
-  // R -> 0 and G3 is strongly curved).  Otherwise *ds3 is NaN.  Why: in a
-  // strongly cooling cell near its root numer / cS is small, so G follows
-  // dt Q_rad(x), a steep convex function of s, and Newton on G creeps down
-  // from above; ln Q_rad is close to linear in s, so Newton on G3 converges
-  // quadratically from much further away.
-  RC_HD double outer(double s, double x, bool on, bool want3, double* z, double* dG, double* q_out,
+  // dz/dx; *ds3 receives a second step proposal, or NaN:
+  //  * mode 1 (an iterate): the Newton step of the log-ratio form
+  //      G3 = ln Pg - ln Ng,
+  //    Pg = dt Q_rad + c (x - T_e)+ + c (z - T_i)+,  Ng = c (T_e - x)+ + c (T_i - z)+,
+  //    the energy gained and lost by the electron-ion pair; G3 has the sign
+  //    of G.  Why: where numer / cS is small G is close to numer / cS, a steep
+  //    exponential of s when radiation dominates, and Newton on G creeps; ln Pg
+  //    and ln Ng are close to linear in s away from x = T_e.
+  //  * mode 2 (the first evaluation of a cooling cell, G > 0): the root of a
+  //    model with power-law cooling of the slope at T_e and the exchange
+  //    terms linear in x,
+  //      ln(dt q) + p d = ln(A (1 - e^d) + R0),  d = s' - s,
+  //    A = c T_e (1 + dz/dx), R0 = c (T_i - z), solved in single precision
+  //    (it is only a proposal; the safeguards of the driver still apply).
+  RC_HD double outer(double s, double x, bool on, int mode, double* z, double* dG, double* q_out,
                      double* K_first, double* dzdx_out, double* ds3) {
     const double lx = s * (1.0 / kLn10);
     double q, dq, dzdx;
@@ -365,14 +370,32 @@ struct CellSolver {
     *q_out = q;
     *dzdx_out = dzdx;
     *ds3 = __builtin_nan("");
-    if (want3) {
-      const double R = c * ((T_e - x) + (T_i - *z));
-      if (q > 0.0 && R > 0.0 && cx <= 2.0 * R) {
-        const double dG3 = dq / q + cx / R;
-        if (dG3 > 0.0) *ds3 = -flog(dt * q / R) / dG3;
+    const double G = flog1p(numer / cS);
+    if (mode == 1) {
+      const double cxz = c * x * dzdx;
+      double Pg = dt * q, Ng = 0.0, dP = dt * dq, dN = 0.0;
+      if (x > T_e) { Pg += c * (x - T_e); dP += c * x; } else { Ng += c * (T_e - x); dN -= c * x; }
+      if (*z > T_i) { Pg += c * (*z - T_i); dP += cxz; } else { Ng += c * (T_i - *z); dN -= cxz; }
+      if (Pg > 0.0 && Ng > 0.0) {
+        const double dG3 = dP / Pg - dN / Ng;
+        if (dG3 > 0.0) *ds3 = -flog(Pg / Ng) / dG3;
       }
+    } else if (mode == 2 && numer > 0.0 && q > 0.0 && *dG > 0.0) {
+      // in base 2: u = d / ln 2, f(u) = L + p u - log2(1 - 2^u + r0),
+      // L = log2(dt q / A), r0 = R0 / A
+      const float p = (float)(dq / q);
+      const float L = flog2_sp((float)(dt * q / cx));
+      const float r0 = (float)(c * (T_i - *z) / cx);
+      float u = (float)(-G / (*dG * kLn2));
+      for (int k = 0; k < 4; ++k) {
+        const float e = fexp2_sp(u);
+        const float R = (1.0f - e) + r0;
+        const float un = u - (L + p * u - flog2_sp(R)) / (p + e / R);
+        u = un < 0.0f ? un : 0.5f * u;
+      }
+      *ds3 = (double)u * kLn2;
     }
-    return flog1p(numer / cS);
+    return G;
   }
 
   // Newton driver.  Every evaluation of the outer residual goes through one
@@ -380,6 +403,7 @@ struct CellSolver {
   // next one), so the inlined rate code exists once in the kernel; the whole
   // iteration state lives in NewtonState, separate from the cell's constants.
   enum { FIRST = 0, ITER = 1, PROBE_ON = 2, PROBE_OFF = 3, FINAL = 4 };
+  static constexpr double kModelMinStep = 0.01;   // in ln T_e
   enum { F_LO_KNOWN = 1, F_FLOOR_PENDING = 2, F_HEATING = 4, F_ON = 8 };
 
   RC_HD void newton_begin(double s0, NewtonState& ns) const {
@@ -399,10 +423,9 @@ struct CellSolver {
     const double tol = P.tol;
     for (;;) {   // one evaluation, plus the z-only one of a cell that converges in it
     const int kind = ns.kind;
-    // the log-log step only serves cooling iterates
-    const bool want3 = kind == ITER && !(ns.flags & F_HEATING) && (ns.flags & F_ON);
+    const int mode = kind == ITER ? 1 : kind == FIRST ? 2 : 0;
     double ze = ns.z, dGe, q, Kf, dzdx_e, ds3;
-    const double Ge = outer(ns.se, ns.xe, (ns.flags & F_ON) != 0, want3, &ze, &dGe, &q, &Kf, &dzdx_e, &ds3);
+    const double Ge = outer(ns.se, ns.xe, (ns.flags & F_ON) != 0, mode, &ze, &dGe, &q, &Kf, &dzdx_e, &ds3);
     if (kind == FINAL) {
       o->T_e_new = ns.xe;
       o->T_i_new = ze;
@@ -484,8 +507,23 @@ struct CellSolver {
       const double s = ns.s, lo = ns.lo, hi = ns.hi;
       const bool lo_known = (ns.flags & F_LO_KNOWN) != 0;
       const bool floor_pending = (ns.flags & F_FLOOR_PENDING) != 0;
-      const bool use3 = (ds3 == ds3) && ns.G > 0.0;   // ds3 is only set on a cooling ITER
-      double sn = use3 ? s + ds3 : s - ns.G / ns.dG;
+      // Choice between the two proposals.  The first step of a cooling cell
+      // takes the model root.  On an iterate both Newton steps point at the
+      // root; G and G3 are convex in s on a cooling cell (radiative loss grows
+      // faster than exponentially in s near the root) and concave on a heating
+      // cell (the Coulomb gain falls with T_e), so of two Newton steps the one
+      // that overshoots less -- the longer on the convex side above the root,
+      // the shorter below it, and the reverse for concave -- is the closer.
+      const bool use3 = (ds3 == ds3);
+      const double dsG = -ns.G / ns.dG;
+      double sn = s + dsG;
+      if (use3) {
+        // the model root is a single-precision estimate: taken only for a
+        // long first step, never as the converged one
+        if (kind == FIRST) sn = dsG < -kModelMinStep ? s + ds3 : sn;
+        else if (!(ns.dG > 0.0)) sn = s + ds3;
+        else sn = s + ((ns.flags & F_HEATING) ? fmax(ds3, dsG) : fmin(ds3, dsG));
+      }
       const bool newton_ok = (use3 || ns.dG > 0.0) && (sn == sn);
       if (newton_ok && fabs(sn - s) <= P.sqrt_tol && !(floor_pending && sn < sf)) {
         // converged: Newton converges quadratically, so once the step is
