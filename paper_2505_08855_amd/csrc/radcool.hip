@@ -167,6 +167,7 @@ void fill_geom(rc_tables_s* t) {
   fill_axes(t->spec, t->geom.ax);
   for (int k = 0; k < 4; ++k)
     for (int j = 0; j < 4; ++j) t->geom.coef[k][j] = t->coef[k][j];
+  for (int j = 0; j < 4; ++j) t->geom.coef_se[j] = t->coef[1][j] + t->coef[2][j];
 }
 
 rc_status upload(rc_tables_s* t, void* stream) {

@@ -32,6 +32,32 @@ constexpr double kInvLn10 = 0x1.bcb7b1526e50ep-2;   // 1 / ln 10
 constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;  // sqrt(1/2)
 
 // ln x for finite x > 0
+// a / b for finite a and a finite nonzero b of normal magnitude: the
+// reciprocal instruction refined by two Newton steps, then the quotient with
+// one residual correction; within an ulp of a / b.  The IEEE sequence adds
+// operand scaling and a fix-up step for the full range, which the solver's
+// positive, moderate denominators do not need.
+RC_HD double fdiv(double a, double b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(fma(-b, r, 1.0), r, r);
+  r = fma(fma(-b, r, 1.0), r, r);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+#else
+  return a / b;
+#endif
+}
+
+// single-precision reciprocal (the hardware instruction on the device)
+RC_HD float frcp_sp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+
 // single-precision 2^y and log2 x for step proposals that need no more than
 // a few digits: the hardware instructions on the device, the C library on
 // the host
@@ -58,7 +84,7 @@ RC_HD double flog(double x) {
     m += m;
     --e;
   }
-  const double f = (m - 1.0) / (m + 1.0);   // m - 1 is exact
+  const double f = fdiv(m - 1.0, m + 1.0);   // m - 1 is exact
   const double s = f * f;
   double p = 1.0 / 21.0;
   p = fma(p, s, 1.0 / 19.0);
@@ -82,7 +108,7 @@ RC_HD double flog10(double x) { return flog(x) * kInvLn10; }
 RC_HD double flog1p(double v) {
   const double u = 1.0 + v;
   if (u == 1.0) return v;
-  return flog(u) * (v / (u - 1.0));
+  return flog(u) * fdiv(v, u - 1.0);
 }
 
 // 2^y for finite y

@@ -65,6 +65,7 @@ struct AxisP {
 struct TableGeom {
   AxisP ax[6];          // cooling (N, T_e, B), Coulomb (n_e, T_e, T_i)
   double coef[4][4];    // affine part of each log2 table in node-index space
+  double coef_se[4];    // coef[1] + coef[2]: the synchrotron and eta tables enter as a sum
 };
 
 // Everything a step kernel needs besides the table memory.
@@ -226,12 +227,11 @@ struct CellSolver {
     }
     const double fN = iN + tN, fB = iB + tB;
     const double* cb = P.g->coef[0];
-    const double* cs = P.g->coef[1];
-    const double* ce = P.g->coef[2];
+    const double* cse = P.g->coef_se;
     Ab = cb[0] + cb[1] * fN + cb[2] * (double)i + cb[3] * fB + lb;
     Sb = cb[2] + hb - lb;
-    Ase = (cs[0] + ce[0]) + (cs[1] + ce[1]) * fN + (cs[2] + ce[2]) * (double)i + (cs[3] + ce[3]) * fB + lse;
-    Sse = (cs[2] + ce[2]) + hse - lse;
+    Ase = cse[0] + cse[1] * fN + cse[2] * (double)i + cse[3] * fB + lse;
+    Sse = cse[2] + hse - lse;
   }
 
   RC_HD void load_coul(int je, int ji) {
@@ -269,13 +269,14 @@ struct CellSolver {
     const double vb = fexp2(Ab + Sb * t) * invH2;
     const double vs = fexp2(Ase + Sse * t) * invH;
     const double qthin = vb + vs;
-    const double dlq = kLn2 * g * (vb * Sb + vs * Sse) / qthin;
+    const double dlq = kLn2 * g * fdiv(vb * Sb + vs * Sse, qthin);
     const double x2 = x * x;
-    const double ta = H * qthin / (4.0 * kSigmaSB * x2 * x2);
+    const double ta = fdiv(H * qthin, 4.0 * kSigmaSB * x2 * x2);
     const double D = 1.0 + kSqrt3 * ta + 1.5 * ta * (ta + tau_sca);
-    *q = qthin / D;
+    const double iD = fdiv(1.0, D);
+    *q = qthin * iD;
     const double dD = (kSqrt3 + 1.5 * (2.0 * ta + tau_sca)) * ta * (dlq - 4.0);
-    *dq = *q * (dlq - dD / D);
+    *dq = *q * (dlq - dD * iD);
   }
 
   // Coulomb coefficient v_c at (T_e coordinate ce, T_i coordinate ci, cell
@@ -311,7 +312,7 @@ struct CellSolver {
       // x == T_i: z = T_i solves E2; implicit derivative dz/dx = dt K / (c + dt K)
       K = kcoul_at(ce, ci0, &dlx, &dlz);
       if (K_first) *K_first = K;
-      *dzdx = dt * K / (c + dt * K);
+      *dzdx = fdiv(dt * K, c + dt * K);
       return lo;
     }
     double dEz = c;
@@ -319,10 +320,10 @@ struct CellSolver {
       K = it == 0 ? kcoul_at(ce, ci0, &dlx, &dlz) : kcoul(ce, z, &dlx, &dlz);
       if (it == 0 && K_first) *K_first = K;
       const double E = c * (z - T_i) + dt * (z - x) * K;
-      dEz = c + dt * K + dt * (z - x) * K * dlz / z;
+      dEz = c + dt * K + dt * (z - x) * K * fdiv(dlz, z);
       if (E == 0.0) break;                  // z is an exact root
       if (E < 0.0) lo = z; else hi = z;
-      const double dz = -E / dEz;
+      const double dz = -fdiv(E, dEz);
       // converged: Newton converges quadratically, so after a step below
       // 1e-8 z the remaining error is ~1e-16 z.  Tested before the bracket
       // safeguard, which would reject a step below the bracket end's ulp.
@@ -332,8 +333,8 @@ struct CellSolver {
       z = zn;
       if (hi - lo <= 1e-15 * z) break;
     }
-    const double dEx = -dt * K + dt * (z - x) * K * dlx / x;
-    *dzdx = -dEx / dEz;
+    const double dEx = -dt * K + dt * (z - x) * K * fdiv(dlx, x);
+    *dzdx = -fdiv(dEx, dEz);
     return z;
   }
 
@@ -366,19 +367,20 @@ struct CellSolver {
     *z = solve_z(x, ce, z0, ci, &dzdx, K_first);
     const double numer = c * ((x - T_e) + (*z - T_i)) + dt * q;
     const double cx = c * x * (1.0 + dzdx);
-    *dG = (cx + dt * dq) / (cS + numer);
+    *dG = fdiv(cx + dt * dq, cS + numer);
     *q_out = q;
     *dzdx_out = dzdx;
     *ds3 = __builtin_nan("");
-    const double G = flog1p(numer / cS);
+    const double G = flog1p(fdiv(numer, cS));
     if (mode == 1) {
       const double cxz = c * x * dzdx;
       double Pg = dt * q, Ng = 0.0, dP = dt * dq, dN = 0.0;
       if (x > T_e) { Pg += c * (x - T_e); dP += c * x; } else { Ng += c * (T_e - x); dN -= c * x; }
       if (*z > T_i) { Pg += c * (*z - T_i); dP += cxz; } else { Ng += c * (T_i - *z); dN -= cxz; }
       if (Pg > 0.0 && Ng > 0.0) {
-        const double dG3 = dP / Pg - dN / Ng;
-        if (dG3 > 0.0) *ds3 = -flog(Pg / Ng) / dG3;
+        const double iP = fdiv(1.0, Pg), iN = fdiv(1.0, Ng);
+        const double dG3 = dP * iP - dN * iN;
+        if (dG3 > 0.0) *ds3 = -fdiv(flog(Pg * iN), dG3);
       }
     } else if (mode == 2 && numer > 0.0 && q > 0.0 && *dG > 0.0) {
       // in base 2: u = d / ln 2, f(u) = L + p u - log2(1 - 2^u + r0),
@@ -390,7 +392,7 @@ struct CellSolver {
       for (int k = 0; k < 4; ++k) {
         const float e = fexp2_sp(u);
         const float R = (1.0f - e) + r0;
-        const float un = u - (L + p * u - flog2_sp(R)) / (p + e / R);
+        const float un = u - (L + p * u - flog2_sp(R)) * frcp_sp(p + e * frcp_sp(R));
         u = un < 0.0f ? un : 0.5f * u;
       }
       *ds3 = (double)u * kLn2;
@@ -402,7 +404,7 @@ struct CellSolver {
   // call site (newton_round: evaluate at the pending point, then choose the
   // next one), so the inlined rate code exists once in the kernel; the whole
   // iteration state lives in NewtonState, separate from the cell's constants.
-  enum { FIRST = 0, ITER = 1, PROBE_ON = 2, PROBE_OFF = 3, FINAL = 4 };
+  enum { FIRST = 0, ITER = 1, PROBE_ON = 2, PROBE_OFF = 3, DONE = 4 };
   static constexpr double kModelMinStep = 0.01;   // in ln T_e
   enum { F_LO_KNOWN = 1, F_FLOOR_PENDING = 2, F_HEATING = 4, F_ON = 8 };
 
@@ -421,16 +423,18 @@ struct CellSolver {
     const double T_floor = Tf();
     const double sf = lnTf();
     const double tol = P.tol;
-    for (;;) {   // one evaluation, plus the z-only one of a cell that converges in it
+    // The loop runs once per evaluation; a converged step loops back to the
+    // DONE exit so that every exit of a converging cell shares one path.
+    for (;;) {
     const int kind = ns.kind;
+    if (kind == DONE) {
+      o->T_e_new = ns.xe;
+      o->T_i_new = ns.z;
+      return true;
+    }
     const int mode = kind == ITER ? 1 : kind == FIRST ? 2 : 0;
     double ze = ns.z, dGe, q, Kf, dzdx_e, ds3;
     const double Ge = outer(ns.se, ns.xe, (ns.flags & F_ON) != 0, mode, &ze, &dGe, &q, &Kf, &dzdx_e, &ds3);
-    if (kind == FINAL) {
-      o->T_e_new = ns.xe;
-      o->T_i_new = ze;
-      return true;
-    }
     bool propose = false;
     // dz/dx at the iterate when this round's evaluation became the iterate;
     // 0 otherwise (the next inner solve then starts from z unchanged)
@@ -530,11 +534,12 @@ struct CellSolver {
         // below sqrt(tol) the error left after taking it is O(tol) -- provided
         // the step stays inside the table cells of the current iterate (the
         // interpolant is smooth inside a cell; across a node its slope jumps
-        // and the step's error is first order in the jump).  Then only z(x)
-        // remains, solved at the new point (cooling off, so that only the
-        // inner solve runs) in this same round, from the first-order warm
-        // start z + dz/dx (x' - x).  Tested before the bracket safeguard,
-        // which could reject a step below an end's ulp.
+        // and the step's error is first order in the jump).  T_i' is the
+        // first-order extrapolation z + dz/dx (x' - x) along the solution
+        // curve z(x) of the ion equation, whose error is second order in
+        // x' - x, so O(tol) too, under the same condition on the Coulomb
+        // cells.  Tested before the bracket safeguard, which could reject a
+        // step below an end's ulp.
         const double xn = fexp(sn);
         const double zn = ns.z + dzdx * (xn - ns.xe);
         const double lxn = sn * (1.0 / kLn10);
@@ -542,7 +547,7 @@ struct CellSolver {
                                 axis_coord(lxn, P.g->ax[4]).i == ie && axis_coord(flog10(zn), P.g->ax[5]).i == ii;
         if (same_cells) {
           ns.z = zn;
-          ns.kind = FINAL; ns.se = sn; ns.xe = xn; ns.flags &= ~F_ON;
+          ns.kind = DONE; ns.xe = xn;
           continue;
         }
       }
