@@ -348,12 +348,14 @@ struct CellSolver {
   //    of G.  Why: where numer / cS is small G is close to numer / cS, a steep
   //    exponential of s when radiation dominates, and Newton on G creeps; ln Pg
   //    and ln Ng are close to linear in s away from x = T_e.
-  //  * mode 2 (the first evaluation of a cooling cell, G > 0): the root of a
-  //    model with power-law cooling of the slope at T_e and the exchange
-  //    terms linear in x,
+  //  * mode 2 (the first evaluation): the root of a model of the cell.  A
+  //    cooling cell (G > 0): power-law cooling of the slope at T_e against
+  //    the exchange terms linear in x,
   //      ln(dt q) + p d = ln(A (1 - e^d) + R0),  d = s' - s,
-  //    A = c T_e (1 + dz/dx), R0 = c (T_i - z), solved in single precision
-  //    (it is only a proposal; the safeguards of the driver still apply).
+  //    A = c T_e (1 + dz/dx), R0 = c (T_i - z).  A heating cell (G < 0): the
+  //    electrons' gain against a power law in x of the ion transfer (below).
+  //    Solved in single precision: it is only a proposal, and the safeguards
+  //    of the driver still apply.
   RC_HD double outer(double s, double x, bool on, int mode, double* z, double* dG, double* q_out,
                      double* K_first, double* dzdx_out, double* ds3) {
     const double lx = s * (1.0 / kLn10);
@@ -382,6 +384,24 @@ struct CellSolver {
         const double dG3 = dP * iP - dN * iN;
         if (dG3 > 0.0) *ds3 = -fdiv(flog(Pg * iN), dG3);
       }
+    } else if (mode == 2 && numer < 0.0 && *dG > 0.0 && *z < T_i) {
+      // first step of a heating cell: the electrons' gain
+      //   c T_e (e^d - 1) + dt q e^(p d)
+      // against the ion transfer N0 e^(b0 d), both slopes taken at T_e; in
+      // base 2 and relative to N0 = c (T_i - z):
+      //   f(u) = log2(a (2^u - 1) + r 2^(p u)) - b0 u
+      const double N0 = c * (T_i - *z);
+      const float a = (float)(c * x / N0), r = (float)(dt * q / N0);
+      const float p = q > 0.0 ? (float)(dq / q) : 0.0f;
+      const float b0 = (float)(-c * x * dzdx / N0);
+      float u = (float)(-G / (*dG * kLn2));
+      for (int k = 0; k < 5; ++k) {
+        const float e = fexp2_sp(u), eq = fexp2_sp(p * u);
+        const float Pn = a * (e - 1.0f) + r * eq;
+        const float un = u - (flog2_sp(Pn) - b0 * u) * frcp_sp((a * e + p * r * eq) * frcp_sp(Pn) - b0);
+        u = un > 0.0f ? un : 0.5f * u;
+      }
+      *ds3 = (double)u * kLn2;
     } else if (mode == 2 && numer > 0.0 && q > 0.0 && *dG > 0.0) {
       // in base 2: u = d / ln 2, f(u) = L + p u - log2(1 - 2^u + r0),
       // L = log2(dt q / A), r0 = R0 / A
@@ -511,8 +531,8 @@ struct CellSolver {
       const double s = ns.s, lo = ns.lo, hi = ns.hi;
       const bool lo_known = (ns.flags & F_LO_KNOWN) != 0;
       const bool floor_pending = (ns.flags & F_FLOOR_PENDING) != 0;
-      // Choice between the two proposals.  The first step of a cooling cell
-      // takes the model root.  On an iterate both Newton steps point at the
+      // Choice between the two proposals.  A long first step takes the model
+      // root.  On an iterate both Newton steps point at the
       // root; G and G3 are convex in s on a cooling cell (radiative loss grows
       // faster than exponentially in s near the root) and concave on a heating
       // cell (the Coulomb gain falls with T_e), so of two Newton steps the one
@@ -524,7 +544,7 @@ struct CellSolver {
       if (use3) {
         // the model root is a single-precision estimate: taken only for a
         // long first step, never as the converged one
-        if (kind == FIRST) sn = dsG < -kModelMinStep ? s + ds3 : sn;
+        if (kind == FIRST) sn = fabs(dsG) > kModelMinStep ? s + ds3 : sn;
         else if (!(ns.dG > 0.0)) sn = s + ds3;
         else sn = s + ((ns.flags & F_HEATING) ? fmax(ds3, dsG) : fmin(ds3, dsG));
       }
