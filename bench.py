@@ -125,6 +125,35 @@ def measured_traffic():
     return rec["traffic_bytes_per_step"] if rec.get("source_hash") == source_hash() else None
 
 
+def measured_valu():
+    """(VALU instructions per wavefront, wavefronts) of the Newton kernel from the
+    committed counter summary, if it matches these sources."""
+    try:
+        with open(TRAFFIC_SUMMARY) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"^traffic-record: (\{.*\})$", text, re.M)
+    if not m or json.loads(m.group(1)).get("source_hash") != source_hash():
+        return None
+    per = re.search(r"^\| SQ_INSTS_VALU per wave \| ([0-9,.]+) \|", text, re.M)
+    waves = re.search(r"^\| SQ_WAVES \| ([0-9,]+) \|", text, re.M)
+    if not per or not waves:
+        return None
+    return float(per.group(1).replace(",", "")), float(waves.group(1).replace(",", ""))
+
+
+def valu_roofline(ms):
+    got = measured_valu()
+    if got is None:
+        return None
+    per_wave, waves = got
+    achieved = per_wave * waves / (ms * 1e-3) / 1e9
+    peak = 1024 * 2.4e9 / 4 / 1e9
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "G wave64 VALU instructions/s",
+            "frac": achieved / peak, "source": os.path.relpath(TRAFFIC_SUMMARY, ROOT)}
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -362,6 +391,11 @@ def main():
                      "traffic": measured_traffic() if (args.workload == "iid256" and table_n == 128 and
                                                        args.scheme == "newton" and args.variant == "auto") else None},
         "table_build_s": t_build,
+        # the Newton kernel is bound by FP64 vector issue, not HBM: the VALU
+        # issue rate against the chip's (1024 SIMDs, one wave64 instruction per
+        # 4 cycles at 2.4 GHz), from the committed SQ counters of this kernel
+        "roofline_valu": valu_roofline(ms) if (args.workload == "iid256" and table_n == 128 and
+                                                args.scheme == "newton" and args.variant == "auto") else None,
         "status_counts": {str(int(v)): int(c) for v, c in zip(*np.unique(status, return_counts=True))},
     }
     if not args.no_variants:
@@ -402,6 +436,36 @@ def main():
             var[name] = {"ms": vms, "Gcell_per_s": n / (vms * 1e-3) / 1e9,
                          "hbm_frac": nbytes * n / (vms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del prims
+        # the paper's own layout: log2 Q_total on a 4-D grid of 100^4 nodes over
+        # the paper's ranges, read by 4-D interpolation (16 corners); speed
+        # against the rates kernel of the 3-D column tables (which also
+        # produces Q_cc), and model error of both layouts against the closed
+        # forms (DIRECT variant) on a sample of the same cells
+        t4 = R.Table4D.build()
+        q4, _ = R.rates4d(t4, state, opts.T_floor)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            q4, _ = R.rates4d(t4, state, opts.T_floor)
+        e1.record()
+        torch.cuda.synchronize()
+        vms = e0.elapsed_time(e1) / 5
+        m = min(n, 1 << 20)
+        sub = {k: v[:m] for k, v in state.items()}
+        qd = R.cool_step(tables, sub, dt, R.default_opts(scheme="rates", variant="direct"))["Q_rad"]
+        q3 = R.cool_step(tables, sub, dt, R.default_opts(scheme="rates"))["Q_rad"]
+        on = qd > 0
+        err = {}
+        for name, qq in (("table4d_100", q4[:m]), ("tables3d_%d" % table_n, q3)):
+            e = ((qq[on] - qd[on]).abs() / qd[on]).cpu().numpy()
+            err[name] = {"median": float(np.median(e)), "p99": float(np.quantile(e, 0.99)), "max": float(e.max())}
+        var["rates_table4d"] = {"ms": vms, "Gcell_per_s": n / (vms * 1e-3) / 1e9,
+                                "table_bytes": 4 * int(np.prod(list(R.paper_axes4().n))),
+                                "q_rad_rel_err_vs_closed_forms": err, "sample_cells": m}
+        t4.destroy()
+        del q4, qd, q3, sub
         # the same step reading bfloat16-stored tables (half the table bytes)
         t16 = R.Tables.build(R.default_spec(table_n, "bf16"))
         vms, _ = time_steps(R, torch, t16, state, dt, opts, out, 3, 1)
