@@ -19,6 +19,13 @@ in optically thick cells, tau_sca = n_e sigma_T H > tau_crit (4.6: fewer than 1 
 of photons escape unscattered), the pressure n_e k_B (T_e + T_i) is shared
 between radiation and gas, a T^4 + n_e k_B (T + T_i) = n_e k_B (T_e + T_i), with
 T_i held; the left side increases with T, so the root T in (0, T_e) is unique.
+
+Downstream coupling (Sec. II.E, eqs. energy-momentum_eq and 4-force_calc): the
+cooling enters the gas's energy-momentum equation as the 4-force density
+G_mu = -lambda u_mu, lambda the radiated energy per unit volume and time; over
+a step of length dt the conserved densities U_mu = sqrt(-g) T^t_mu change by
+dt sqrt(-g) G_mu.  The lambda that matches a step's temperature update is the
+energy it removed from the gas, 1.5 n_e k_B [(T_e - T_e') + (T_i - T_i')] / dt.
 """
 import numpy as np
 
@@ -95,4 +102,24 @@ def step_with_gas_floor(ts, n_e, T_e, T_i, B, H, dt, T_floor_gas, T_floor=1.0e6,
         for k, v in part.items():
             out[k][mask] = v
     out["status"] = np.where(off, out["status"] | ST_GAS_FLOOR, out["status"]).astype(np.uint8)
+    return out
+
+
+def cooling_lambda(n_e, T_e, T_i, T_e_new, T_i_new, dt):
+    """Energy per unit volume and time the step removed from the gas [erg cm^-3 s^-1]."""
+    n_e, T_e, T_i, T_e_new, T_i_new = (np.asarray(v, dtype=np.float64) for v in (n_e, T_e, T_i, T_e_new, T_i_new))
+    return 1.5 * n_e * K.K_B * ((T_e - T_e_new) + (T_i - T_i_new)) / dt
+
+
+def apply_cooling(U, u_cov, lam, dt, sqrt_g=None):
+    """U_mu + dt sqrt(-g) G_mu with G_mu = -lambda u_mu; U and u_cov are
+    sequences of four arrays (mu = 0..3).  Cells whose lambda is not finite keep
+    U.  Returns the new list of four arrays."""
+    lam = np.asarray(lam, dtype=np.float64)
+    sg = np.ones_like(lam) if sqrt_g is None else np.asarray(sqrt_g, dtype=np.float64)
+    ok = np.isfinite(lam)
+    out = []
+    for mu in range(4):
+        G = -lam * np.asarray(u_cov[mu], dtype=np.float64)
+        out.append(np.where(ok, np.asarray(U[mu], dtype=np.float64) + dt * sg * G, U[mu]))
     return out

@@ -82,3 +82,77 @@ def test_rad_pressure_correction_limits_and_residual():
     # T^4 = (n k / a)(T_e - T): the leading correction is T / (4 T_e) ~ (n k / (a T_e^3))^(1/4) / 4
     eps = (n_e[m] * K.K_B / (U.A_RAD * T_e[m] ** 3)) ** 0.25
     assert np.all(rel_err(T[m], (n_e[m] * K.K_B * T_e[m] / U.A_RAD) ** 0.25) < 0.5 * eps)
+
+
+# ------------------------------------------------------------------ downstream coupling
+
+
+def _boosted(n, seed):
+    """Covariant 4-velocities of random boosts in flat space (signature -+++)
+    and the matching contravariant ones."""
+    rng = np.random.default_rng(seed)
+    v = rng.uniform(-0.5, 0.5, (n, 3))
+    g = 1.0 / np.sqrt(1.0 - (v ** 2).sum(1))
+    up = [g] + [g * v[:, k] for k in range(3)]
+    down = [-g] + [g * v[:, k] for k in range(3)]
+    return down, up
+
+
+def test_coupling_in_the_fluid_frame_removes_lambda_dt_from_the_energy():
+    """u_mu = (-1, 0, 0, 0), sqrt(-g) = 1: only U_0 = T^t_t = -e changes, by
+    +lambda dt, i.e. the energy density falls by the radiated energy."""
+    n = 16
+    rng = np.random.default_rng(5)
+    lam = 10.0 ** rng.uniform(-5, 5, n)
+    U0 = [rng.normal(size=n) for _ in range(4)]
+    u = [-np.ones(n), np.zeros(n), np.zeros(n), np.zeros(n)]
+    dt = 0.37
+    out = U.apply_cooling(U0, u, lam, dt)
+    assert np.max(rel_err(out[0], U0[0] + lam * dt)) < 1e-14
+    for mu in (1, 2, 3):
+        assert np.array_equal(out[mu], U0[mu])
+
+
+def test_coupling_contracts_to_the_invariant_lambda():
+    """G_mu u^mu = -lambda u_mu u^mu = lambda for any boost: the energy the
+    fluid loses in its own frame does not depend on the observer."""
+    n = 64
+    down, up = _boosted(n, 8)
+    rng = np.random.default_rng(9)
+    lam = 10.0 ** rng.uniform(-3, 3, n)
+    sg = rng.uniform(0.5, 2.0, n)
+    U0 = [np.zeros(n) for _ in range(4)]
+    dt = 1.3
+    out = U.apply_cooling(U0, down, lam, dt, sqrt_g=sg)
+    contr = sum(out[mu] * up[mu] for mu in range(4))
+    assert np.max(rel_err(contr, dt * sg * lam)) < 1e-12
+
+
+def test_coupling_skips_cells_without_a_finite_lambda():
+    n = 4
+    U0 = [np.arange(n, dtype=float) + mu for mu in range(4)]
+    down, _ = _boosted(n, 3)
+    lam = np.array([1.0, np.nan, np.inf, 0.0])
+    out = U.apply_cooling(U0, down, lam, 2.0)
+    for mu in range(4):
+        assert np.array_equal(out[mu][1:], U0[mu][1:])
+        assert out[mu][0] == U0[mu][0] - 2.0 * down[mu][0]
+
+
+def test_lambda_of_a_backward_euler_step_is_the_cooling_at_the_new_state(ts64, cells0_small):
+    """Backward Euler balances the energies at the end of the step:
+    c [(T_e' - T_e) + (T_i' - T_i)] = -dt Q_rad(T_e'), so the coupling's lambda is
+    the radiative cooling evaluated at the new temperatures (cells above the
+    floor; to the energy tier of the solve)."""
+    from oracle import step as S
+    from paper_2505_08855_amd import workloads as W
+    c = {k: cells0_small[k][:512] for k in W.FIELDS}
+    dt = W.DT_DEFAULT * 1e2
+    out = S.step_be(ts64, *[c[f] for f in W.FIELDS], dt)
+    lam = U.cooling_lambda(c["n_e"], c["T_e"], c["T_i"], out["T_e_new"], out["T_i_new"], dt)
+    new = S.table_rates(ts64, c["n_e"], out["T_e_new"], out["T_i_new"], c["B"], c["H"])
+    keep = (out["status"] & 8) == 0          # not projected onto the floor
+    q_new = np.where(out["T_e_new"] >= 1.0e6, new["q_rad"], 0.0)
+    u = 1.5 * c["n_e"] * K.K_B * (c["T_e"] + c["T_i"])
+    assert keep.sum() > 400
+    assert np.max(np.abs(lam - q_new)[keep] * dt / u[keep]) < 1e-9
