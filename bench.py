@@ -436,6 +436,28 @@ def main():
             var[name] = {"ms": vms, "Gcell_per_s": n / (vms * 1e-3) / 1e9,
                          "hbm_frac": nbytes * n / (vms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del prims
+        # downstream coupling: the step's cooling applied to the gas
+        # energy-momentum in place; reads n_e, T_e, T_i, T_e', T_i', u_mu (4),
+        # sqrt(-g), U_mu (4) and writes U_mu (4) and lambda: 152 B per cell
+        R.cool_step(tables, state, dt, opts, out=out)
+        z0 = torch.zeros(n, dtype=torch.float64, device=dev)
+        u_cov = [-torch.ones(n, dtype=torch.float64, device=dev), z0, z0.clone(), z0.clone()]
+        U_cons = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(4)]
+        sqrt_g = torch.ones(n, dtype=torch.float64, device=dev)
+        fwd = {"T_e_new": out["T_e_new"], "T_i_new": out["T_i_new"]}
+        lam = R.apply_cooling(state, fwd, u_cov, U_cons, dt, sqrt_g=sqrt_g)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            R.apply_cooling(state, fwd, u_cov, U_cons, dt, sqrt_g=sqrt_g)
+        e1.record()
+        torch.cuda.synchronize()
+        vms = e0.elapsed_time(e1) / 5
+        var["apply_cooling"] = {"ms": vms, "Gcell_per_s": n / (vms * 1e-3) / 1e9,
+                                "hbm_frac": 152 * n / (vms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del z0, u_cov, U_cons, sqrt_g, lam, fwd
         # the paper's own layout: log2 Q_total on a 4-D grid of 100^4 nodes over
         # the paper's ranges, read by 4-D interpolation (16 corners); speed
         # against the rates kernel of the 3-D column tables (which also

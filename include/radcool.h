@@ -325,6 +325,38 @@ rc_status rc_disk_inputs(const double* rho, const double* P, const double* u, co
 rc_status rc_rad_pressure_correction(const double* n_e, const double* T_e, const double* H, int64_t n,
                                      double tau_crit, double* T_e_out, uint8_t* thick, void* stream);
 
+/* Downstream coupling of the cooling to the gas (Sec. II.E, eqs.
+ * energy-momentum_eq and 4-force_calc): the 4-force density
+ * G_mu = -lambda u_mu applied over dt to the conserved energy-momentum
+ * densities U_mu = sqrt(-g) T^t_mu,
+ *   U_mu += dt sqrt(-g) G_mu = -dt sqrt(-g) lambda u_mu,
+ * with lambda the energy per unit volume and time the step removed from the
+ * gas [erg cm^-3 s^-1],
+ *   lambda = 1.5 n_e k_B [(T_e - T_e') + (T_i - T_i')] / dt,
+ * which for the backward-Euler step equals Q_rad at the new temperatures.  In
+ * the fluid frame (u_mu = (-1, 0, 0, 0)) U_0 = -e sqrt(-g) rises by
+ * dt sqrt(-g) lambda: the gas energy falls by the radiated energy.
+ *   u_cov:  covariant 4-velocity u_0..u_3 (dimensionless, c = 1), required;
+ *   sqrt_g: sqrt(-g) per cell, NULL for 1;
+ *   U:      the four conserved densities, updated in place (the caller's
+ *           units, consistent with lambda dt); a NULL component is skipped.
+ * Device pointers, FP64 SoA, length n; the library keeps none of them. */
+typedef struct {
+  const double* u_cov[4];
+  const double* sqrt_g;
+  double* U[4];
+} rc_coupling;
+
+/* Apply the cooling of a step (its input temperatures T_e, T_i and outputs
+ * T_e_new, T_i_new) to the gas energy-momentum as above; lambda (may be NULL)
+ * receives the per-cell lambda.  A cell whose lambda is not finite (an
+ * invalid step) keeps U and gets lambda = NaN.  RC_EINVAL for n < 0, dt not
+ * finite and positive, coupling NULL, or a NULL temperature, n_e or velocity
+ * pointer with n > 0.  Asynchronous on stream. */
+rc_status rc_apply_cooling(const double* n_e, const double* T_e, const double* T_i, const double* T_e_new,
+                           const double* T_i_new, int64_t n, double dt, const rc_coupling* coupling, double* lambda,
+                           void* stream);
+
 /* The paper's own cooling-table layout (Sec. II.F, III.A), for comparison
  * with the exact 3-D column tables: log2 of the bridged Q_total on a 4-D grid
  * over log10 H [cm], log10 B [G], log10 n_e [cm^-3], log10 T_e [K] (node k of
@@ -393,6 +425,12 @@ rc_status rc_selftest_disk_host(const double* rho, const double* P, const double
                                 const rc_disk_params* params, double* H_th, double* T_floor_gas);
 rc_status rc_selftest_radp_host(const double* n_e, const double* T_e, const double* H, int64_t n, double tau_crit,
                                 double* T_e_out, uint8_t* thick);
+
+/* Host-side self-test of rc_apply_cooling: the same per-cell source on host
+ * arrays (rc_coupling pointing to host memory).  For tests only. */
+rc_status rc_selftest_coupling_host(const double* n_e, const double* T_e, const double* T_i, const double* T_e_new,
+                                    const double* T_i_new, int64_t n, double dt, const rc_coupling* coupling,
+                                    double* lambda);
 
 /* Host-side self-tests of the 4-D table: node values (log2 Q_total at the
  * given states) and the rates read from host FP32 values.  For tests only. */

@@ -1,5 +1,6 @@
-// Per-cell inputs upstream of the cooling step and the post-processing
-// radiation-pressure temperature correction (host and device).
+// Per-cell inputs upstream of the cooling step, the post-processing
+// radiation-pressure temperature correction and the cooling rate handed
+// downstream (host and device).
 //
 // Thermal scale height (Sec. II.F, eq. H_thermal): H_th = c_s / Omega_K,
 // c_s^2 = gamma P / (rho h) with the relativistic enthalpy density
@@ -60,6 +61,12 @@ RC_HD double rad_pressure_temperature(double n_e, double T_e) {
     if (ds <= 1e-15 * fabs(s)) break;
   }
   return fexp(s);
+}
+
+// energy per unit volume and time a step removed from the gas (the lambda of
+// the 4-force density G_mu = -lambda u_mu, Sec. II.E)
+RC_HD double cooling_lambda(double n_e, double T_e, double T_i, double T_e_new, double T_i_new, double dt) {
+  return kUperNKT * n_e * kKB * ((T_e - T_e_new) + (T_i - T_i_new)) / dt;
 }
 
 }  // namespace rc

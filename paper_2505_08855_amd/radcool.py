@@ -32,7 +32,8 @@ EXPORTED = ("rc_default_spec", "rc_default_opts", "rc_build_tables", "rc_tables_
             "rc_plan_create", "rc_plan_launch", "rc_plan_info", "rc_plan_destroy",
             "rc_disk_inputs", "rc_rad_pressure_correction", "rc_selftest_disk_host", "rc_selftest_radp_host",
             "rc_paper_axes4", "rc_build_table4d", "rc_table4d_import", "rc_table4d_export", "rc_table4d_destroy",
-            "rc_rates4d", "rc_selftest_node4d_host", "rc_selftest_rates4d_host")
+            "rc_rates4d", "rc_selftest_node4d_host", "rc_selftest_rates4d_host", "rc_apply_cooling",
+            "rc_selftest_coupling_host")
 MAX_STATES = 64
 
 
@@ -85,6 +86,10 @@ class Grad(ctypes.Structure):
 class DiskParams(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("spin", ctypes.c_double), ("h_floor", ctypes.c_double),
                 ("r_g", ctypes.c_double)]
+
+
+class Coupling(ctypes.Structure):
+    _fields_ = [("u_cov", ctypes.c_void_p * 4), ("sqrt_g", ctypes.c_void_p), ("U", ctypes.c_void_p * 4)]
 
 
 class Axes4(ctypes.Structure):
@@ -144,6 +149,8 @@ def lib():
             "rc_rad_pressure_correction": (i32, [vp, vp, vp, i64, dbl, vp, vp, vp]),
             "rc_selftest_disk_host": (i32, [vp, vp, vp, vp, i64, P(DiskParams), vp, vp]),
             "rc_selftest_radp_host": (i32, [vp, vp, vp, i64, dbl, vp, vp]),
+            "rc_apply_cooling": (i32, [vp, vp, vp, vp, vp, i64, dbl, P(Coupling), vp, vp]),
+            "rc_selftest_coupling_host": (i32, [vp, vp, vp, vp, vp, i64, dbl, P(Coupling), vp]),
             "rc_paper_axes4": (i32, [P(Axes4), i32]),
             "rc_build_table4d": (i32, [P(Axes4), vp, P(vp)]),
             "rc_table4d_import": (i32, [P(Axes4), vp, vp, P(vp)]),
@@ -548,6 +555,50 @@ def selftest_radp_host(n_e, T_e, H, tau_crit=TAU_CRIT):
     ptr = lambda v: v.ctypes.data_as(ctypes.c_void_p)
     check(lib().rc_selftest_radp_host(*[ptr(v) for v in a], a[0].size, float(tau_crit), ptr(T), ptr(thick)))
     return T, thick
+
+
+def _coupling(u_cov, U, sqrt_g, ptr):
+    c = Coupling()
+    for mu in range(4):
+        c.u_cov[mu] = ptr(u_cov[mu])
+        c.U[mu] = ptr(U[mu]) if U[mu] is not None else None
+    c.sqrt_g = ptr(sqrt_g) if sqrt_g is not None else None
+    return c
+
+
+def apply_cooling(state, fwd, u_cov, U, dt, sqrt_g=None, want_lambda=True, stream=None):
+    """Apply a step's cooling to the gas energy-momentum in place:
+    U[mu] += -dt sqrt(-g) lambda u_cov[mu].  state: n_e, T_e, T_i; fwd: T_e_new,
+    T_i_new; u_cov: four tensors; U: four tensors (or None to skip); all
+    contiguous float64 device tensors of one length.  Returns lambda (or None)."""
+    import torch
+    n = state["n_e"].numel()
+    ts = [state["n_e"], state["T_e"], state["T_i"], fwd["T_e_new"], fwd["T_i_new"]] + list(u_cov)
+    ts += [t for t in U if t is not None] + ([sqrt_g] if sqrt_g is not None else [])
+    for t in ts:
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+            raise ValueError("inputs must be contiguous float64 HIP tensors of equal length")
+    lam = torch.empty(n, dtype=torch.float64, device=state["n_e"].device) if want_lambda else None
+    c = _coupling(u_cov, U, sqrt_g, lambda t: t.data_ptr())
+    check(lib().rc_apply_cooling(state["n_e"].data_ptr(), state["T_e"].data_ptr(), state["T_i"].data_ptr(),
+                                 fwd["T_e_new"].data_ptr(), fwd["T_i_new"].data_ptr(), n, float(dt),
+                                 ctypes.byref(c), lam.data_ptr() if lam is not None else None,
+                                 _stream_ptr(stream)))
+    return lam
+
+
+def selftest_coupling_host(n_e, T_e, T_i, T_e_new, T_i_new, u_cov, U, dt, sqrt_g=None):
+    """rc_apply_cooling's per-cell code on host arrays (test use).  Returns
+    (new U list, lambda)."""
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (n_e, T_e, T_i, T_e_new, T_i_new)]
+    u = [np.ascontiguousarray(v, dtype=np.float64) for v in u_cov]
+    Un = [None if v is None else np.array(v, dtype=np.float64, copy=True) for v in U]
+    sg = None if sqrt_g is None else np.ascontiguousarray(sqrt_g, dtype=np.float64)
+    lam = np.empty_like(a[0])
+    ptr = lambda v: v.ctypes.data_as(ctypes.c_void_p).value
+    c = _coupling(u, Un, sg, ptr)
+    check(lib().rc_selftest_coupling_host(*[ptr(v) for v in a], a[0].size, float(dt), ctypes.byref(c), ptr(lam)))
+    return Un, lam
 
 
 # ---------------------------------------------------------------- the paper's 4-D table layout

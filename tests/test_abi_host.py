@@ -118,3 +118,20 @@ def test_selftest_argument_checks(L):
         op = R.default_opts(**{field: val})
         assert L.rc_selftest_step_host(ctypes.byref(s), P(resid), P(co), *[P(x)] * 5, None, 1, 1e-8,
                                        ctypes.byref(op), None, None, None, None, None) == -1, field
+
+
+def test_apply_cooling_rejects_bad_arguments(L):
+    """Host-side argument checks of rc_apply_cooling (nothing is launched)."""
+    c = R.Coupling()
+    one = np.ones(4)
+    p = one.ctypes.data_as(ctypes.c_void_p).value
+    for mu in range(4):
+        c.u_cov[mu] = p
+    args = [p] * 5
+    assert L.rc_apply_cooling(*args, -1, 1.0, ctypes.byref(c), None, None) == -1      # n < 0
+    assert L.rc_apply_cooling(*args, 4, 0.0, ctypes.byref(c), None, None) == -1       # dt <= 0
+    assert L.rc_apply_cooling(*args, 4, float("nan"), ctypes.byref(c), None, None) == -1
+    assert L.rc_apply_cooling(*args, 4, 1.0, None, None, None) == -1                  # coupling NULL
+    c.u_cov[2] = None
+    assert L.rc_apply_cooling(*args, 4, 1.0, ctypes.byref(c), None, None) == -1       # velocity NULL
+    assert L.rc_apply_cooling(*args, 0, 1.0, ctypes.byref(c), None, None) == 0        # empty: no-op

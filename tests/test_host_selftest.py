@@ -294,3 +294,40 @@ def test_converged_step_may_not_cross_a_table_node():
     ref = S.step_be(S.TableSet(spec, st), *[cell[k] for k in W.FIELDS], DT)
     for k in ("T_e_new", "T_i_new"):
         assert rel_err(got[k], ref[k])[0] < 1e-12, k
+
+
+def _coupling_case(n, seed):
+    rng = np.random.default_rng(seed)
+    ne = 10 ** rng.uniform(10, 20, n)
+    te = 10 ** rng.uniform(7, 11, n)
+    ti = te * 10 ** rng.uniform(0, 2, n)
+    ten = te * (1 - rng.uniform(-0.5, 0.5, n))
+    tin = ti * (1 - rng.uniform(-0.01, 0.01, n))
+    v = rng.uniform(-0.5, 0.5, (n, 3))
+    g = 1.0 / np.sqrt(1.0 - (v ** 2).sum(1))
+    u = [-g] + [g * v[:, k] for k in range(3)]
+    U0 = [rng.normal(size=n) * 1e3 for _ in range(4)]
+    sg = rng.uniform(0.5, 2.0, n)
+    return ne, te, ti, ten, tin, u, U0, sg
+
+
+def test_apply_cooling_on_host():
+    """The coupling's per-cell code against the oracle: lambda exactly, U to
+    rounding; an invalid step (NaN temperature) keeps U; a NULL U component is
+    skipped; sqrt(-g) defaults to 1."""
+    from oracle import upstream as U
+    ne, te, ti, ten, tin, u, U0, sg = _coupling_case(257, 3)
+    ten[7] = np.nan
+    dt = 4.9e-8
+    for sgv in (sg, None):
+        Un, lam = R.selftest_coupling_host(ne, te, ti, ten, tin, u, U0, dt, sgv)
+        ref_l = U.cooling_lambda(ne, te, ti, ten, tin, dt)
+        ref_U = U.apply_cooling(U0, u, ref_l, dt, sqrt_g=sgv)
+        ok = np.isfinite(ref_l)
+        assert not ok[7] and np.isnan(lam[7])
+        assert np.max(rel_err(lam[ok], ref_l[ok])) < 1e-15
+        for mu in range(4):
+            assert np.max(rel_err(Un[mu], ref_U[mu])) < 1e-13
+            assert Un[mu][7] == U0[mu][7]
+    Un, _ = R.selftest_coupling_host(ne, te, ti, ten, tin, u, [U0[0], None, U0[2], None], dt)
+    assert Un[1] is None and Un[3] is None
