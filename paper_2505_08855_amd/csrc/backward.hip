@@ -49,7 +49,7 @@ struct AtomicScatter {
 };
 
 template <class Tab>
-__global__ __launch_bounds__(256) void k_backward(Tab tab, StepParams P, BwdArgs a, int64_t n) {
+__global__ __launch_bounds__(256, 2) void k_backward(Tab tab, StepParams P, BwdArgs a, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   AtomicScatter sc{a.o_tab, a.o_tab ? a.o_tab + 3 * a.vc : nullptr, a.g_se};
