@@ -49,7 +49,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = 5 * 8 + 4 * 8 + 1      # state in, T', Q_rad, Q_cc out, status
 COPY_BYTES = 64 << 23                   # the calibration copy: 512 MiB read and written
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "newton_iid256_t128_counters.md")
-STEP_KERNELS = re.compile(r"k_step<0, rc::GlobalTab>")   # the Newton kernel (demangled name), FP32 tables
+STEP_KERNELS = re.compile(r"k_step<0, rc::CellTab>")     # the Newton kernel (demangled name), FP32 tables
 
 
 def source_hash():
@@ -401,9 +401,11 @@ def main():
     if not args.no_variants:
         var = {}
         for name, kw, steps in (("newton_block256", dict(block=256), 3),
-                                ("rates_global", dict(scheme="rates"), 5),
-                                ("explicit16_global", dict(scheme="explicit16"), 3),
+                                ("rates", dict(scheme="rates"), 5),
+                                ("explicit16", dict(scheme="explicit16"), 3),
                                 ("rates_direct", dict(scheme="rates", variant="direct"), 1),
+                                ("newton_global", dict(variant="global"), 3),
+                                ("rates_global", dict(scheme="rates", variant="global"), 5),
                                 ("newton_lds", dict(variant="lds"), 3),
                                 ("rates_lds", dict(scheme="rates", variant="lds"), 5)):
             o = R.default_opts(**kw)

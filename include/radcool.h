@@ -128,8 +128,9 @@ typedef struct {
 
 enum { RC_SCHEME_NEWTON = 0, RC_SCHEME_EXPLICIT16 = 1, RC_SCHEME_RATES = 2 };
 
-/* How the tables are read.  GLOBAL (what AUTO selects) gathers the corners
- * with plain global loads, through the vector L1 and L2 caches.  LDS stages,
+/* How the tables are read.  AUTO selects CELL for FP32 tables and GLOBAL for
+ * bfloat16 tables.  GLOBAL gathers the corners with plain global loads,
+ * through the vector L1 and L2 caches.  LDS stages,
  * per workgroup, the box of table nodes its cells can reach (their N and B
  * cells of the cooling tables over the whole T_e axis, their n_e cells of the
  * Coulomb table over the whole T_e x T_i plane) in 256 bytes of LDS per
@@ -139,8 +140,17 @@ enum { RC_SCHEME_NEWTON = 0, RC_SCHEME_EXPLICIT16 = 1, RC_SCHEME_RATES = 2 };
  * 256).  It pays only for spatially coherent cell order.  TEX names the texture-memory path
  * of the paper's GPU (Sec. III.A); gfx950 exposes no texture sampling to HIP,
  * so it returns RC_EUNSUPPORTED.  DIRECT evaluates the closed forms of
- * Sec. II per cell instead of tables (rates scheme only). */
-enum { RC_VARIANT_AUTO = 0, RC_VARIANT_GLOBAL = 1, RC_VARIANT_LDS = 2, RC_VARIANT_TEX = 3, RC_VARIANT_DIRECT = 4 };
+ * Sec. II per cell instead of tables (rates scheme only).  CELL reads a
+ * cell-blocked copy of the FP32 tables, the 8 corners of every table cell
+ * stored together (a cooling cell's 8 x 16 bytes fill one 128-byte cache
+ * line), so that a corner gather touches one line instead of four, for 8
+ * times the table memory (about 256 MiB more at 128^3 nodes).  The copy is
+ * built on the first CELL (or AUTO) call for an FP32 table set: that call
+ * allocates device memory and synchronizes its stream; later calls do
+ * neither (make one call before capturing a graph).  Results equal GLOBAL's.
+ * RC_EUNSUPPORTED for bfloat16 tables. */
+enum { RC_VARIANT_AUTO = 0, RC_VARIANT_GLOBAL = 1, RC_VARIANT_LDS = 2, RC_VARIANT_TEX = 3, RC_VARIANT_DIRECT = 4,
+       RC_VARIANT_CELL = 5 };
 
 typedef struct {
   int32_t scheme;        /* RC_SCHEME_*: backward Euler (Newton), 16-substep explicit, or rates only */

@@ -3,6 +3,7 @@
 // the launch of the per-cell step kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -210,6 +211,65 @@ rc_status upload(rc_tables_s* t, void* stream) {
   return RC_OK;
 }
 
+// cell-blocked copies: corner (a, b, c) of cell (i0, i1, i2) at
+// ((i0 (n1 - 1) + i1) (n2 - 1) + i2) 8 + a 4 + b 2 + c
+__global__ __launch_bounds__(256) void k_cells_cool(const float4* nodes, float4* cells, int n0, int n1, int n2) {
+  const int64_t total = (int64_t)(n0 - 1) * (n1 - 1) * (n2 - 1) * 8;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(j & 7);
+    int64_t c = j >> 3;
+    const int i2 = (int)(c % (n2 - 1));
+    c /= (n2 - 1);
+    const int i1 = (int)(c % (n1 - 1));
+    const int i0 = (int)(c / (n1 - 1));
+    cells[j] = nodes[((int64_t)(i0 + (k >> 2)) * n1 + i1 + ((k >> 1) & 1)) * n2 + i2 + (k & 1)];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cells_coul(const float* nodes, float* cells, int n0, int n1, int n2) {
+  const int64_t total = (int64_t)(n0 - 1) * (n1 - 1) * (n2 - 1) * 8;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(j & 7);
+    int64_t c = j >> 3;
+    const int i2 = (int)(c % (n2 - 1));
+    c /= (n2 - 1);
+    const int i1 = (int)(c % (n1 - 1));
+    const int i0 = (int)(c / (n1 - 1));
+    cells[j] = nodes[((int64_t)(i0 + (k >> 2)) * n1 + i1 + ((k >> 1) & 1)) * n2 + i2 + (k & 1)];
+  }
+}
+
+rc_status ensure_cells(rc_tables_s* t, hipStream_t s) {
+  if (t->spec.value_dtype != RC_VALUE_F32)
+    return set_error(RC_EUNSUPPORTED, "the cell-blocked table layout holds FP32 tables only");
+  std::lock_guard<std::mutex> lock(t->cells_lock);
+  if (t->d_cool_cells && t->d_coul_cells) return RC_OK;
+  const rc_axes &a = t->spec.cool, &k = t->spec.coul;
+  const int64_t nc = (int64_t)(a.n[0] - 1) * (a.n[1] - 1) * (a.n[2] - 1) * 8;
+  const int64_t nk = (int64_t)(k.n[0] - 1) * (k.n[1] - 1) * (k.n[2] - 1) * 8;
+  void *dc = nullptr, *dk = nullptr;
+  hipError_t e = hipMalloc(&dc, sizeof(float4) * nc);
+  if (e == hipSuccess) e = hipMalloc(&dk, sizeof(float) * nk);
+  if (e == hipSuccess) {
+    const auto grid = [](int64_t m) { return (unsigned)std::min<int64_t>((m + 255) / 256, 1 << 16); };
+    hipLaunchKernelGGL(k_cells_cool, dim3(grid(nc)), dim3(256), 0, s, (const float4*)t->d_cool, (float4*)dc, a.n[0],
+                       a.n[1], a.n[2]);
+    hipLaunchKernelGGL(k_cells_coul, dim3(grid(nk)), dim3(256), 0, s, (const float*)t->d_coul, (float*)dk, k.n[0],
+                       k.n[1], k.n[2]);
+    e = hipGetLastError();
+    // complete before the pointers become visible to calls on other streams
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  if (e != hipSuccess) {
+    if (dc) (void)hipFree(dc);
+    if (dk) (void)hipFree(dk);
+    return hip_fail(e, "building the cell-blocked tables");
+  }
+  t->d_cool_cells = dc;
+  t->d_coul_cells = dk;
+  return RC_OK;
+}
+
 void destroy_tables(rc_tables_s* t) {
   if (!t) return;
   if (t->d_geom) (void)hipFree(t->d_geom);
@@ -217,6 +277,8 @@ void destroy_tables(rc_tables_s* t) {
   if (t->d_coul) (void)hipFree(t->d_coul);
   if (t->d_counter) (void)hipFree(t->d_counter);
   if (t->d_gscratch) (void)hipFree(t->d_gscratch);
+  if (t->d_cool_cells) (void)hipFree(t->d_cool_cells);
+  if (t->d_coul_cells) (void)hipFree(t->d_coul_cells);
   t->magic = 0;
   delete t;
 }

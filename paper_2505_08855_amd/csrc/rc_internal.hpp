@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "radcool.h"
@@ -29,6 +30,10 @@ struct rc_tables_s {
   rc::TableGeom* d_geom = nullptr;  // the same in device memory, read by the kernels
   void* d_counter = nullptr;        // work-queue counter of the batched kernel (allocated on first use)
   void* d_gscratch = nullptr;       // backward: synch * eta table-gradient accumulator (first use)
+  // cell-blocked copies of the FP32 tables (RC_VARIANT_CELL; built on first use)
+  void* d_cool_cells = nullptr;
+  void* d_coul_cells = nullptr;
+  std::mutex cells_lock;
 };
 
 namespace rc {
@@ -46,6 +51,10 @@ void fill_geom(rc_tables_s* t);
 rc_status make_params(rc_tables t, double dt, const rc_step_opts* o, StepParams* P, bool host = false);
 // host copy of residuals in their storage form (bfloat16-rounded for that form)
 std::vector<float> storage_values(const rc_table_spec& s, const float* resid);
+
+// Build the cell-blocked copies of t's FP32 tables on stream s if they do not
+// exist yet (allocates; ordered before later work on s).
+rc_status ensure_cells(rc_tables_s* t, hipStream_t s);
 
 // Call f with the table accessor of t's storage form (GlobalTab or GlobalTabBF16).
 template <class F>

@@ -100,6 +100,20 @@ RC_HD Coord axis_coord(double u, const AxisP& a) {
 // Table memory in global memory: cooling tables interleaved per node as
 // {brem, synch, eta, 0} (one 16-byte load per corner serves all three), the
 // Coulomb table planar; both C-ordered [i0][i1][i2].
+// the 8 corners of the table cell with lowest corner (i0, i1, i2) through an
+// accessor's single-node reads, corner (a, b, c) at a * 4 + b * 2 + c
+template <class T>
+RC_HD void corners8(const T& t, int i0, int i1, int i2, float4 (&v)[8]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = t.cool_at(i0 + (k >> 2), i1 + ((k >> 1) & 1), i2 + (k & 1));
+}
+
+template <class T>
+RC_HD void corners8c(const T& t, int i0, int i1, int i2, float (&v)[8]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = t.coul_at(i0 + (k >> 2), i1 + ((k >> 1) & 1), i2 + (k & 1));
+}
+
 struct GlobalTab {
   const float4* cool;
   const float* coul;
@@ -107,6 +121,8 @@ struct GlobalTab {
   int k1, k2;           // Coulomb n1, n2
   RC_HD float4 cool_at(int i0, int i1, int i2) const { return cool[((long)i0 * c1 + i1) * c2 + i2]; }
   RC_HD float coul_at(int i0, int i1, int i2) const { return coul[((long)i0 * k1 + i1) * k2 + i2]; }
+  RC_HD void cool8(int i0, int i1, int i2, float4 (&v)[8]) const { corners8(*this, i0, i1, i2, v); }
+  RC_HD void coul8(int i0, int i1, int i2, float (&v)[8]) const { corners8c(*this, i0, i1, i2, v); }
 };
 
 // bfloat16 bits -> float (exact: bfloat16 is the upper half of a binary32)
@@ -126,6 +142,34 @@ struct GlobalTabBF16 {
     return make_float4(bf16_to_float(p.x & 0xffffu), bf16_to_float(p.x >> 16), bf16_to_float(p.y & 0xffffu), 0.0f);
   }
   RC_HD float coul_at(int i0, int i1, int i2) const { return bf16_to_float(coul[((long)i0 * k1 + i1) * k2 + i2]); }
+  RC_HD void cool8(int i0, int i1, int i2, float4 (&v)[8]) const { corners8(*this, i0, i1, i2, v); }
+  RC_HD void coul8(int i0, int i1, int i2, float (&v)[8]) const { corners8c(*this, i0, i1, i2, v); }
+};
+
+// The FP32 tables with a cell-blocked copy: the 8 corners of every table cell
+// stored together, corner (a, b, c) at a * 4 + b * 2 + c (cooling: 8 float4,
+// 128 bytes, one cache line; Coulomb: 8 floats, 32 bytes).  A corner gather
+// then touches one line instead of four, for 8 times the table memory.  The
+// node layout stays for the single-corner reads.
+struct CellTab {
+  const float4* cool;
+  const float* coul;
+  const float4* cool_cells;
+  const float* coul_cells;
+  int c1, c2;
+  int k1, k2;
+  RC_HD float4 cool_at(int i0, int i1, int i2) const { return cool[((long)i0 * c1 + i1) * c2 + i2]; }
+  RC_HD float coul_at(int i0, int i1, int i2) const { return coul[((long)i0 * k1 + i1) * k2 + i2]; }
+  RC_HD void cool8(int i0, int i1, int i2, float4 (&v)[8]) const {
+    const float4* p = cool_cells + (((long)i0 * (c1 - 1) + i1) * (c2 - 1) + i2) * 8;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = p[k];
+  }
+  RC_HD void coul8(int i0, int i1, int i2, float (&v)[8]) const {
+    const float* p = coul_cells + (((long)i0 * (k1 - 1) + i1) * (k2 - 1) + i2) * 8;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = p[k];
+  }
 };
 
 struct CellOut {
@@ -212,13 +256,15 @@ struct CellSolver {
     const double wN[2] = {1.0 - tN, tN};
     const double wB[2] = {1.0 - tB, tB};
     double lb = 0.0, lse = 0.0, hb = 0.0, hse = 0.0;
+    float4 v[8];
+    tab.cool8(iN, i, iB, v);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         const double w = wN[a] * wB[b];
-        const float4 p = tab.cool_at(iN + a, i, iB + b);
-        const float4 q = tab.cool_at(iN + a, i + 1, iB + b);
+        const float4 p = v[a * 4 + b];
+        const float4 q = v[a * 4 + 2 + b];
         lb += w * (double)p.x;
         lse += w * ((double)p.y + (double)p.z);
         hb += w * (double)q.x;
@@ -238,10 +284,12 @@ struct CellSolver {
     ie = je;
     ii = ji;
     const double w0 = 1.0 - tn, w1 = tn;
-    v00 = w0 * tab.coul_at(in_, je, ji) + w1 * tab.coul_at(in_ + 1, je, ji);
-    v10 = w0 * tab.coul_at(in_, je + 1, ji) + w1 * tab.coul_at(in_ + 1, je + 1, ji);
-    v01 = w0 * tab.coul_at(in_, je, ji + 1) + w1 * tab.coul_at(in_ + 1, je, ji + 1);
-    v11 = w0 * tab.coul_at(in_, je + 1, ji + 1) + w1 * tab.coul_at(in_ + 1, je + 1, ji + 1);
+    float v[8];
+    tab.coul8(in_, je, ji, v);
+    v00 = w0 * v[0] + w1 * v[4];
+    v10 = w0 * v[2] + w1 * v[6];
+    v01 = w0 * v[1] + w1 * v[5];
+    v11 = w0 * v[3] + w1 * v[7];
     const double* co = P.g->coef[3];
     K0 = co[0] + co[1] * (in_ + tn) + co[2] * (double)je + co[3] * (double)ji;
   }
@@ -644,6 +692,8 @@ struct CellSolver {
     const double wB[2] = {1.0 - tB, tB};
     const double wT[2] = {1.0 - cT.t, cT.t};
     double y[3] = {0.0, 0.0, 0.0};
+    float4 v[8];
+    tab.cool8(iN, cT.i, iB, v);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -651,7 +701,7 @@ struct CellSolver {
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           const double w = wN[a] * wT[m] * wB[b];
-          const float4 p = tab.cool_at(iN + a, cT.i + m, iB + b);
+          const float4 p = v[a * 4 + m * 2 + b];
           y[0] += w * (double)p.x;
           y[1] += w * (double)p.y;
           y[2] += w * (double)p.z;

@@ -21,7 +21,7 @@ TAB_BREM, TAB_SYNCH, TAB_ETA, TAB_COUL = 0, 1, 2, 3
 ST_INVALID, ST_CLAMP_COOL, ST_CLAMP_COUL, ST_FLOOR, ST_MAXITER, ST_GAS_FLOOR = 1, 2, 4, 8, 16, 32
 SCHEME_NEWTON, SCHEME_EXPLICIT16, SCHEME_RATES = 0, 1, 2
 VARIANT_AUTO, VARIANT_GLOBAL, VARIANT_LDS, VARIANT_TEX, VARIANT_DIRECT = 0, 1, 2, 3, 4
-VARIANTS = {"auto": 0, "global": 1, "lds": 2, "tex": 3, "direct": 4}
+VARIANTS = {"auto": 0, "global": 1, "lds": 2, "tex": 3, "direct": 4, "cell": 5}
 SCHEMES = {"newton": 0, "explicit16": 1, "rates": 2}
 
 EXPORTED = ("rc_default_spec", "rc_default_opts", "rc_build_tables", "rc_tables_import",
