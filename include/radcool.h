@@ -230,9 +230,11 @@ typedef struct {
  * of n_blocks entries; blocks whose range lies outside [0, n_total) or whose
  * state_id is outside [0, n_states) are skipped.  dt_per_state is a host array
  * of n_states (1 .. RC_MAX_STATES) positive finite values.  Same per-cell
- * semantics as rc_cool_step.  Uses an internal 4-byte device counter
- * allocated on first use per table handle; calls that overlap on one table
- * handle must use the same stream.  Asynchronous on stream. */
+ * semantics as rc_cool_step; variants AUTO, GLOBAL and CELL (AUTO reads the
+ * cell-blocked copy of FP32 tables, built on first use as described for
+ * RC_VARIANT_CELL), others RC_EUNSUPPORTED.  Uses an internal 4-byte device
+ * counter allocated on first use per table handle; calls that overlap on one
+ * table handle must use the same stream.  Asynchronous on stream. */
 rc_status rc_cool_step_batched(rc_tables t, const rc_state* state, int64_t n_total, const rc_block* blocks,
                                int32_t n_blocks, const double* dt_per_state, int32_t n_states,
                                const rc_step_opts* opts, const rc_out* out, void* stream);
@@ -244,7 +246,9 @@ rc_status rc_cool_step_batched(rc_tables t, const rc_state* state, int64_t n_tot
  * workgroups per compute unit) are chosen by timing each candidate with HIP
  * events on the given stream (the outputs are written during tuning).
  * blocks is copied to the host once to validate every range (RC_EINVAL).
- * The plan keeps pointers, not copies, of state, out and blocks. */
+ * The plan keeps pointers, not copies, of state, out and blocks; the
+ * cell-blocked table copy, when the variant reads it, is built before the
+ * capture. */
 typedef struct rc_plan_s* rc_plan;
 rc_status rc_plan_create(rc_tables t, const rc_state* state, int64_t n_total, const rc_block* blocks,
                          int32_t n_blocks, const double* dt_per_state, int32_t n_states,

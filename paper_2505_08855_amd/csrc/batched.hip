@@ -73,8 +73,8 @@ rc_status check_batch_args(rc_tables t, const rc_state* state, int64_t n_total, 
     if (!(dts[k] > 0.0) || !std::isfinite(dts[k])) return set_error(RC_EINVAL, "batched: dt_per_state must be finite and > 0");
   rc_status st = make_params(t, dts[0], opts, P);
   if (st != RC_OK) return st;
-  if (opts->variant != RC_VARIANT_AUTO && opts->variant != RC_VARIANT_GLOBAL)
-    return set_error(RC_EUNSUPPORTED, "batched: only the global-table variant is batched");
+  if (opts->variant != RC_VARIANT_AUTO && opts->variant != RC_VARIANT_GLOBAL && opts->variant != RC_VARIANT_CELL)
+    return set_error(RC_EUNSUPPORTED, "batched: only the global-table and cell-blocked variants are batched");
   if (n_blocks > 0 && !blocks) return set_error(RC_EINVAL, "batched: blocks is NULL");
   if (n_total > 0 && (!state->n_e || !state->T_e || !state->T_i || !state->B || !state->H))
     return set_error(RC_EINVAL, "batched: a state pointer is NULL");
@@ -97,10 +97,16 @@ rc_status fill_scratch(void* scratch, const double* dts, int n_states, hipStream
   return e == hipSuccess ? RC_OK : hip_fail(e, "batched: copying dt_per_state");
 }
 
-hipError_t launch_batched(int scheme, const rc_tables_s* t, const StepParams& P, const StateArgs& s,
+// the cell-blocked copy serves AUTO (FP32 tables) and CELL
+bool batched_cells(const rc_tables_s* t, const rc_step_opts* opts) {
+  return opts->variant == RC_VARIANT_CELL ||
+         (opts->variant == RC_VARIANT_AUTO && t->spec.value_dtype == RC_VALUE_F32);
+}
+
+hipError_t launch_batched(int scheme, const rc_tables_s* t, bool cells, const StepParams& P, const StateArgs& s,
                           const OutArgs& o, const BatchArgs& b, int block, int grid, hipStream_t hs) {
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, hs, b.counter);
-  with_tab(t, [&](auto tab) {
+  const auto launch = [&](auto tab) {
     using Tab = decltype(tab);
     if (scheme == RC_SCHEME_NEWTON)
       hipLaunchKernelGGL((k_batched<SCHEME_NEWTON, Tab>), dim3(grid), dim3(block), 0, hs, tab, P, s, o, b);
@@ -109,7 +115,14 @@ hipError_t launch_batched(int scheme, const rc_tables_s* t, const StepParams& P,
     else
       hipLaunchKernelGGL((k_batched<SCHEME_RATES, Tab>), dim3(grid), dim3(block), 0, hs, tab, P, s, o, b);
     return 0;
-  });
+  };
+  if (cells) {
+    const rc_table_spec& sp = t->spec;
+    launch(CellTab{(const float4*)t->d_cool, (const float*)t->d_coul, (const float4*)t->d_cool_cells,
+                   (const float*)t->d_coul_cells, sp.cool.n[1], sp.cool.n[2], sp.coul.n[1], sp.coul.n[2]});
+  } else {
+    with_tab(t, launch);
+  }
   return hipGetLastError();
 }
 
@@ -133,6 +146,7 @@ struct rc_plan_s {
   OutArgs o;
   BatchArgs b;
   int scheme = 0;
+  bool cells = false;   // the step reads the cell-blocked table copy
   int block = 256, grid = 0;
   double tuned_ms = 0.0;
   unsigned* counter = nullptr;
@@ -150,6 +164,8 @@ extern "C" rc_status rc_cool_step_batched(rc_tables t, const rc_state* state, in
   rc_status st = check_batch_args(t, state, n_total, blocks, n_blocks, dt_per_state, n_states, opts, out, &P, &b);
   if (st != RC_OK) return st;
   if (n_blocks == 0 || n_total == 0) return RC_OK;
+  const bool cells = batched_cells(t, opts);
+  if (cells && (st = ensure_cells(t, (hipStream_t)stream)) != RC_OK) return st;
   if (!t->d_counter) {
     const hipError_t ae = hipMalloc(&t->d_counter, kBatchScratch);
     if (ae != hipSuccess) return hip_fail(ae, "hipMalloc(batched scratch)");
@@ -160,7 +176,7 @@ extern "C" rc_status rc_cool_step_batched(rc_tables t, const rc_state* state, in
   OutArgs o{out->T_e_new, out->T_i_new, out->Q_rad, out->Q_cc, out->Q_brem, out->Q_syn, out->eta, out->status};
   const int block = opts->block ? opts->block : 256;
   const int grid = compute_units() * 4;
-  const hipError_t e = launch_batched(opts->scheme, t, P, s, o, b, block, grid, (hipStream_t)stream);
+  const hipError_t e = launch_batched(opts->scheme, t, cells, P, s, o, b, block, grid, (hipStream_t)stream);
   return e == hipSuccess ? RC_OK : hip_fail(e, "rc_cool_step_batched launch");
 }
 
@@ -192,6 +208,11 @@ extern "C" rc_status rc_plan_create(rc_tables t, const rc_state* state, int64_t 
   p->o = OutArgs{out->T_e_new, out->T_i_new, out->Q_rad, out->Q_cc, out->Q_brem, out->Q_syn, out->eta, out->status};
   p->b = b;
   p->scheme = opts->scheme;
+  p->cells = batched_cells(t, opts);
+  if (p->cells && (st = ensure_cells(t, hs)) != RC_OK) {   // before any capture
+    delete p;
+    return st;
+  }
   e = hipMalloc(&p->counter, kBatchScratch);
   if (e != hipSuccess) { delete p; return hip_fail(e, "rc_plan_create: hipMalloc(counter)"); }
   st = fill_scratch(p->counter, dt_per_state, n_states, hs, &p->b);
@@ -210,9 +231,9 @@ extern "C" rc_status rc_plan_create(rc_tables t, const rc_state* state, int64_t 
     for (int bi = 0; bi < 3; ++bi) {
       for (int gi = 0; gi < 4; ++gi) {
         const int blk = blocks_c[bi], grid = cus * per_cu[gi];
-        e = launch_batched(p->scheme, t, p->P, p->s, p->o, p->b, blk, grid, hs);   // warm-up
+        e = launch_batched(p->scheme, t, p->cells, p->P, p->s, p->o, p->b, blk, grid, hs);   // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, hs);
-        if (e == hipSuccess) e = launch_batched(p->scheme, t, p->P, p->s, p->o, p->b, blk, grid, hs);
+        if (e == hipSuccess) e = launch_batched(p->scheme, t, p->cells, p->P, p->s, p->o, p->b, blk, grid, hs);
         if (e == hipSuccess) e = hipEventRecord(e1, hs);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.0f;
@@ -236,7 +257,7 @@ extern "C" rc_status rc_plan_create(rc_tables t, const rc_state* state, int64_t 
   e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    const hipError_t le = launch_batched(p->scheme, t, p->P, p->s, p->o, p->b, p->block, p->grid, cap);
+    const hipError_t le = launch_batched(p->scheme, t, p->cells, p->P, p->s, p->o, p->b, p->block, p->grid, cap);
     e = hipStreamEndCapture(cap, &p->graph);
     if (le != hipSuccess) e = le;
   }
