@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "radcool.h"
@@ -24,6 +25,8 @@ struct BwdArgs {
   const double *g_x, *g_z, *g_qr, *g_qc;
   double *o_n, *o_Te, *o_Ti, *o_B, *o_H, *o_tab;
   double* g_se;           // scratch: gradient shared by the synch and eta entries
+  double* g_cool_cells;   // scratch, cell-blocked: {brem, synch * eta} per corner of each cooling cell
+  double* g_coul_cells;   // scratch, cell-blocked: one value per corner of each Coulomb cell
   int c1, c2, k1, k2;
   long vc;
   int newton;
@@ -48,11 +51,42 @@ struct AtomicScatter {
   }
 };
 
-template <class Tab>
+// Table-gradient scatter into cell-blocked scratch: the corners of one table
+// cell are contiguous (cooling: 8 x {brem, synch * eta} doubles = 128 bytes,
+// Coulomb: 8 doubles), so one evaluation's atomics land in one or two cache
+// lines instead of eight; k_finish_cells folds the cells back onto the nodes.
+struct CellScatter {
+  double* g_cool;
+  double* g_coul;
+  int c1, c2, k1, k2;
+  // cell whose lowest corner is node idx0 of a table with n1 x n2 trailing nodes
+  __device__ static long cell_of(long idx0, int n1, int n2) {
+    const long i2 = idx0 % n2, r = idx0 / n2;
+    const long i1 = r % n1, i0 = r / n1;
+    return (i0 * (n1 - 1) + i1) * (n2 - 1) + i2;
+  }
+  __device__ void cool(const long* idx, const double* vb, const double* vse) const {
+    double* base = g_cool + cell_of(idx[0], c1, c2) * 16;
+    for (int k = 0; k < 8; ++k) {
+      if (vb[k] != 0.0) atomicAdd(base + 2 * k, vb[k]);
+      if (vse[k] != 0.0) atomicAdd(base + 2 * k + 1, vse[k]);
+    }
+  }
+  __device__ void coul(const long* idx, const double* vc) const {
+    double* base = g_coul + cell_of(idx[0], k1, k2) * 8;
+    for (int k = 0; k < 8; ++k)
+      if (vc[k] != 0.0) atomicAdd(base + k, vc[k]);
+  }
+};
+
+template <class Tab, bool CELLS>
 __global__ __launch_bounds__(256, 2) void k_backward(Tab tab, StepParams P, BwdArgs a, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  AtomicScatter sc{a.o_tab, a.o_tab ? a.o_tab + 3 * a.vc : nullptr, a.g_se};
+  using Scatter = typename std::conditional<CELLS, CellScatter, AtomicScatter>::type;
+  Scatter sc;
+  if constexpr (CELLS) sc = CellScatter{a.g_cool_cells, a.g_coul_cells, a.c1, a.c2, a.k1, a.k2};
+  else sc = AtomicScatter{a.o_tab, a.o_tab ? a.o_tab + 3 * a.vc : nullptr, a.g_se};
   CellGrad g;
   const double x = a.newton ? a.x[i] : a.T_e[i];
   const double z = a.newton ? a.z[i] : a.T_i[i];
@@ -70,6 +104,40 @@ __global__ __launch_bounds__(256, 2) void k_backward(Tab tab, StepParams P, BwdA
 
 __global__ void k_zero(double* p, long n) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+// fold cell-blocked gradients onto the nodes: node (i0, i1, i2) is corner
+// (a, b, m) of cell (i0 - a, i1 - b, i2 - m) wherever that cell exists; the
+// synch * eta gradient goes to both tables' slots
+__global__ void k_finish_cells(double* g_tab, const double* cool_cells, const double* coul_cells, int n0, int n1,
+                               int n2, int m0, int m1, int m2) {
+  const long vc = (long)n0 * n1 * n2, vk = (long)m0 * m1 * m2;
+  for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j < vc + vk; j += (long)gridDim.x * blockDim.x) {
+    const bool cl = j < vc;
+    const long v = cl ? j : j - vc;
+    const int d0 = cl ? n0 : m0, d1 = cl ? n1 : m1, d2 = cl ? n2 : m2;
+    const int i2 = (int)(v % d2), i1 = (int)((v / d2) % d1), i0 = (int)(v / ((long)d1 * d2));
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = 0; k < 8; ++k) {
+      const int a = k >> 2, b = (k >> 1) & 1, m = k & 1;
+      const int c0 = i0 - a, c1 = i1 - b, c2 = i2 - m;
+      if (c0 < 0 || c1 < 0 || c2 < 0 || c0 > d0 - 2 || c1 > d1 - 2 || c2 > d2 - 2) continue;
+      const long cell = ((long)c0 * (d1 - 1) + c1) * (d2 - 1) + c2;
+      if (cl) {
+        s0 += cool_cells[cell * 16 + 2 * k];
+        s1 += cool_cells[cell * 16 + 2 * k + 1];
+      } else {
+        s0 += coul_cells[cell * 8 + k];
+      }
+    }
+    if (cl) {
+      g_tab[v] += s0;
+      g_tab[vc + v] += s1;
+      g_tab[2 * vc + v] += s1;
+    } else {
+      g_tab[3 * vc + v] += s0;
+    }
+  }
 }
 
 // add the shared synch * eta gradient to both tables' slots
@@ -128,19 +196,29 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
   if (grid > 0x7fffffffLL) return set_error(RC_EINVAL, "rc_cool_step_backward: n too large for one launch");
   hipStream_t hs = (hipStream_t)stream;
   a.g_se = nullptr;
+  a.g_cool_cells = a.g_coul_cells = nullptr;
+  const rc_axes &ca = t->spec.cool, &ka = t->spec.coul;
+  const long ncc = (long)(ca.n[0] - 1) * (ca.n[1] - 1) * (ca.n[2] - 1) * 16;
+  const long nkc = (long)(ka.n[0] - 1) * (ka.n[1] - 1) * (ka.n[2] - 1) * 8;
   if (a.o_tab) {
     if (!t->d_gscratch) {
-      const hipError_t ae = hipMalloc(&t->d_gscratch, sizeof(double) * a.vc);
+      const hipError_t ae = hipMalloc(&t->d_gscratch, sizeof(double) * (ncc + nkc));
       if (ae != hipSuccess) return hip_fail(ae, "hipMalloc(table-gradient scratch)");
     }
-    a.g_se = (double*)t->d_gscratch;
-    hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, hs, a.g_se, a.vc);
+    a.g_cool_cells = (double*)t->d_gscratch;
+    a.g_coul_cells = a.g_cool_cells + ncc;
+    hipLaunchKernelGGL(k_zero, dim3(4096), dim3(256), 0, hs, a.g_cool_cells, ncc + nkc);
   }
   with_tab(t, [&](auto tab) {
-    hipLaunchKernelGGL(k_backward<decltype(tab)>, dim3((unsigned)grid), dim3(block), 0, hs, tab, P, a, n);
+    if (a.o_tab)
+      hipLaunchKernelGGL((k_backward<decltype(tab), true>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, a, n);
+    else
+      hipLaunchKernelGGL((k_backward<decltype(tab), false>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, a, n);
     return 0;
   });
-  if (a.o_tab) hipLaunchKernelGGL(k_finish_se, dim3(1024), dim3(256), 0, hs, a.o_tab, a.g_se, a.vc);
+  if (a.o_tab)
+    hipLaunchKernelGGL(k_finish_cells, dim3(4096), dim3(256), 0, hs, a.o_tab, (const double*)a.g_cool_cells,
+                       (const double*)a.g_coul_cells, ca.n[0], ca.n[1], ca.n[2], ka.n[0], ka.n[1], ka.n[2]);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "rc_cool_step_backward launch");
   return RC_OK;
