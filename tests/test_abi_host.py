@@ -135,3 +135,29 @@ def test_apply_cooling_rejects_bad_arguments(L):
     c.u_cov[2] = None
     assert L.rc_apply_cooling(*args, 4, 1.0, ctypes.byref(c), None, None) == -1       # velocity NULL
     assert L.rc_apply_cooling(*args, 0, 1.0, ctypes.byref(c), None, None) == 0        # empty: no-op
+
+
+def test_variant_names_match_the_header():
+    """The binding's variant names carry the header's enum values, and the
+    library accepts each of them and rejects the next value (host check, no
+    launch: the host self-test runs the per-cell code on the CPU)."""
+    src = open(os.path.join(ROOT, "include", "radcool.h")).read()
+    enum = dict((k.lower(), int(v)) for k, v in re.findall(r"RC_VARIANT_(\w+) = (\d+)", src))
+    assert enum == R.VARIANTS
+    s = R.default_spec(4)
+    n = 4 * 4 * 4
+    resid = np.zeros(4 * n, dtype=np.float32)
+    co = np.zeros(16)
+    x = np.ones(1)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    L = R.lib()
+    for name, val in R.VARIANTS.items():
+        if name == "direct":
+            continue          # rates scheme only
+        op = R.default_opts(variant=name)
+        assert L.rc_selftest_step_host(ctypes.byref(s), P(resid), P(co), *[P(x)] * 5, None, 1, 1e-8,
+                                       ctypes.byref(op), None, None, None, None, None) == 0, name
+    op = R.default_opts()
+    op.variant = max(R.VARIANTS.values()) + 1
+    assert L.rc_selftest_step_host(ctypes.byref(s), P(resid), P(co), *[P(x)] * 5, None, 1, 1e-8,
+                                   ctypes.byref(op), None, None, None, None, None) == -1
