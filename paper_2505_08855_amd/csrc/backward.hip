@@ -27,6 +27,8 @@ struct BwdArgs {
   double* g_se;           // scratch: gradient shared by the synch and eta entries
   double* g_cool_cells;   // scratch, cell-blocked: {brem, synch * eta} per corner of each cooling cell
   double* g_coul_cells;   // scratch, cell-blocked: one value per corner of each Coulomb cell
+  unsigned *key_cool, *key_coul, *cnt_cool, *cnt_coul;   // gradient records (see RecordScatter)
+  double *rec_cool, *rec_coul;
   int c1, c2, k1, k2;
   long vc;
   int newton;
@@ -36,6 +38,7 @@ struct BwdArgs {
 // the caller's array, the shared synch * eta gradient into library scratch
 // (added to both tables' slots by k_finish_se).
 struct AtomicScatter {
+  enum { kRecords = 0 };
   double* g_brem;
   double* g_coul;
   double* g_se;
@@ -51,31 +54,35 @@ struct AtomicScatter {
   }
 };
 
-// Table-gradient scatter into cell-blocked scratch: the corners of one table
-// cell are contiguous (cooling: 8 x {brem, synch * eta} doubles = 128 bytes,
-// Coulomb: 8 doubles), so one evaluation's atomics land in one or two cache
-// lines instead of eight; k_finish_cells folds the cells back onto the nodes.
-struct CellScatter {
-  double* g_cool;
-  double* g_coul;
-  int c1, c2, k1, k2;
-  // cell whose lowest corner is node idx0 of a table with n1 x n2 trailing nodes
-  __device__ static long cell_of(long idx0, int n1, int n2) {
-    const long i2 = idx0 % n2, r = idx0 / n2;
-    const long i1 = r % n1, i0 = r / n1;
-    return (i0 * (n1 - 1) + i1) * (n2 - 1) + i2;
+// Table-gradient records: the adjoint writes, per cell and evaluation point,
+// the table cell it fell in, its coefficients and fractional coordinates
+// (cooling: cb, cse, t0, t1, t2; Coulomb: cc, t0, t1, t2) and counts the
+// records of each table cell; a counting sort by table cell then lets one
+// thread per table cell add up its records' corner contributions without
+// atomics on the gradients.  Record r = 2 i + p of cell i and point p; its key
+// is ~0u when the point contributes nothing.
+struct RecordScatter {
+  enum { kRecords = 1 };
+  unsigned* key_cool;
+  double* rec_cool;
+  unsigned* cnt_cool;
+  unsigned* key_coul;
+  double* rec_coul;
+  unsigned* cnt_coul;
+  long r0;
+  __device__ void cool_rec(int p, long cell, double cb, double cse, const double* t) const {
+    const long r = r0 + p;
+    double* q = rec_cool + r * 5;
+    q[0] = cb; q[1] = cse; q[2] = t[0]; q[3] = t[1]; q[4] = t[2];
+    key_cool[r] = (unsigned)cell;
+    atomicAdd(cnt_cool + cell, 1u);
   }
-  __device__ void cool(const long* idx, const double* vb, const double* vse) const {
-    double* base = g_cool + cell_of(idx[0], c1, c2) * 16;
-    for (int k = 0; k < 8; ++k) {
-      if (vb[k] != 0.0) atomicAdd(base + 2 * k, vb[k]);
-      if (vse[k] != 0.0) atomicAdd(base + 2 * k + 1, vse[k]);
-    }
-  }
-  __device__ void coul(const long* idx, const double* vc) const {
-    double* base = g_coul + cell_of(idx[0], k1, k2) * 8;
-    for (int k = 0; k < 8; ++k)
-      if (vc[k] != 0.0) atomicAdd(base + k, vc[k]);
+  __device__ void coul_rec(int p, long cell, double cc, const double* t) const {
+    const long r = r0 + p;
+    double* q = rec_coul + r * 4;
+    q[0] = cc; q[1] = t[0]; q[2] = t[1]; q[3] = t[2];
+    key_coul[r] = (unsigned)cell;
+    atomicAdd(cnt_coul + cell, 1u);
   }
 };
 
@@ -83,10 +90,15 @@ template <class Tab, bool CELLS>
 __global__ __launch_bounds__(256, 2) void k_backward(Tab tab, StepParams P, BwdArgs a, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  using Scatter = typename std::conditional<CELLS, CellScatter, AtomicScatter>::type;
+  using Scatter = typename std::conditional<CELLS, RecordScatter, AtomicScatter>::type;
   Scatter sc;
-  if constexpr (CELLS) sc = CellScatter{a.g_cool_cells, a.g_coul_cells, a.c1, a.c2, a.k1, a.k2};
-  else sc = AtomicScatter{a.o_tab, a.o_tab ? a.o_tab + 3 * a.vc : nullptr, a.g_se};
+  if constexpr (CELLS) {
+    sc = RecordScatter{a.key_cool, a.rec_cool, a.cnt_cool, a.key_coul, a.rec_coul, a.cnt_coul, 2 * i};
+    a.key_cool[2 * i] = a.key_cool[2 * i + 1] = ~0u;
+    a.key_coul[2 * i] = a.key_coul[2 * i + 1] = ~0u;
+  } else {
+    sc = AtomicScatter{a.o_tab, a.o_tab ? a.o_tab + 3 * a.vc : nullptr, a.g_se};
+  }
   CellGrad g;
   const double x = a.newton ? a.x[i] : a.T_e[i];
   const double z = a.newton ? a.z[i] : a.T_i[i];
@@ -104,6 +116,70 @@ __global__ __launch_bounds__(256, 2) void k_backward(Tab tab, StepParams P, BwdA
 
 __global__ void k_zero(double* p, long n) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+__global__ void k_zero_u32(unsigned* p, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// exclusive scan of 1024-element chunks (one workgroup each); chunk totals to sums
+__global__ __launch_bounds__(1024) void k_scan_chunks(const unsigned* in, unsigned* out, unsigned* sums, long n) {
+  __shared__ unsigned buf[1024];
+  const long i = blockIdx.x * 1024L + threadIdx.x;
+  const unsigned v = i < n ? in[i] : 0u;
+  buf[threadIdx.x] = v;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const unsigned add = threadIdx.x >= (unsigned)d ? buf[threadIdx.x - d] : 0u;
+    __syncthreads();
+    buf[threadIdx.x] += add;
+    __syncthreads();
+  }
+  if (i < n) out[i] = buf[threadIdx.x] - v;
+  if (threadIdx.x == 1023) sums[blockIdx.x] = buf[1023];
+}
+
+__global__ void k_scan_add(unsigned* out, const unsigned* offs, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    out[i] += offs[i / 1024];
+}
+
+// place record indices by table cell (cursor starts as the exclusive scan)
+__global__ void k_order(const unsigned* key, unsigned* cursor, unsigned* order, long nrec) {
+  for (long r = blockIdx.x * (long)blockDim.x + threadIdx.x; r < nrec; r += (long)gridDim.x * blockDim.x) {
+    const unsigned k = key[r];
+    if (k != ~0u) order[atomicAdd(cursor + k, 1u)] = (unsigned)r;
+  }
+}
+
+// one thread per table cell: the corner contributions of its records, written
+// to the cell-blocked gradient scratch (zero for a cell without records)
+template <bool COOL>
+__global__ void k_gather_records(const unsigned* start, const unsigned* cnt, const unsigned* order,
+                                 const double* rec, double* cells, long ncell) {
+  for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < ncell; c += (long)gridDim.x * blockDim.x) {
+    double acc0[8], acc1[8];
+    for (int k = 0; k < 8; ++k) acc0[k] = acc1[k] = 0.0;
+    const unsigned b = start[c], m = cnt[c];
+    for (unsigned j = 0; j < m; ++j) {
+      const double* q = rec + (long)order[b + j] * (COOL ? 5 : 4);
+      const double c0 = q[0], c1 = COOL ? q[1] : 0.0;
+      const double t0 = q[COOL ? 2 : 1], t1 = q[COOL ? 3 : 2], t2 = q[COOL ? 4 : 3];
+      for (int k = 0; k < 8; ++k) {
+        const double w = ((k >> 2) ? t0 : 1.0 - t0) * (((k >> 1) & 1) ? t1 : 1.0 - t1) * ((k & 1) ? t2 : 1.0 - t2);
+        acc0[k] += c0 * w;
+        if (COOL) acc1[k] += c1 * w;
+      }
+    }
+    if (COOL) {
+      for (int k = 0; k < 8; ++k) {
+        cells[c * 16 + 2 * k] = acc0[k];
+        cells[c * 16 + 2 * k + 1] = acc1[k];
+      }
+    } else {
+      for (int k = 0; k < 8; ++k) cells[c * 8 + k] = acc0[k];
+    }
+  }
 }
 
 // fold cell-blocked gradients onto the nodes: node (i0, i1, i2) is corner
@@ -146,6 +222,17 @@ __global__ void k_finish_se(double* g_tab, const double* g_se, long vc) {
     const double v = g_se[i];
     g_tab[vc + i] += v;
     g_tab[2 * vc + i] += v;
+  }
+}
+
+// exclusive scan of m counts into out; tmp holds the chunk sums of every
+// level (at most 2 ceil(m / 1024) + 2 entries)
+void scan_counts(const unsigned* in, unsigned* out, long m, unsigned* tmp, hipStream_t hs) {
+  const long nb = (m + 1023) / 1024;
+  hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)nb), dim3(1024), 0, hs, in, out, tmp, m);
+  if (nb > 1) {
+    scan_counts(tmp, tmp, nb, tmp + nb, hs);
+    hipLaunchKernelGGL(k_scan_add, dim3(4096), dim3(256), 0, hs, out, (const unsigned*)tmp, m);
   }
 }
 
@@ -197,28 +284,70 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
   hipStream_t hs = (hipStream_t)stream;
   a.g_se = nullptr;
   a.g_cool_cells = a.g_coul_cells = nullptr;
+  a.key_cool = a.key_coul = a.cnt_cool = a.cnt_coul = nullptr;
+  a.rec_cool = a.rec_coul = nullptr;
   const rc_axes &ca = t->spec.cool, &ka = t->spec.coul;
-  const long ncc = (long)(ca.n[0] - 1) * (ca.n[1] - 1) * (ca.n[2] - 1) * 16;
-  const long nkc = (long)(ka.n[0] - 1) * (ka.n[1] - 1) * (ka.n[2] - 1) * 8;
+  const long mc = (long)(ca.n[0] - 1) * (ca.n[1] - 1) * (ca.n[2] - 1);   // table cells
+  const long mk = (long)(ka.n[0] - 1) * (ka.n[1] - 1) * (ka.n[2] - 1);
+  const long nrec = 2 * n;                                               // records per table kind
+  if (nrec > 0xfffffffeLL) return set_error(RC_EINVAL, "rc_cool_step_backward: n too large for the gradient records");
+  // scratch: [cooling cells x 16][Coulomb cells x 8][cooling records x 5][Coulomb records x 4] doubles, then
+  // uint32: keys, orders (2 x nrec each), counts, starts, cursors (3 x (mc + mk)), scan sums
+  const long sc_c = 2 * ((mc + 1023) / 1024) + 2, sc_k = 2 * ((mk + 1023) / 1024) + 2;
+  const size_t dbl = sizeof(double) * (size_t)(16 * mc + 8 * mk + 9 * nrec);
+  const size_t u32 = sizeof(unsigned) * (size_t)(4 * nrec + 3 * (mc + mk) + sc_c + sc_k);
   if (a.o_tab) {
-    if (!t->d_gscratch) {
-      const hipError_t ae = hipMalloc(&t->d_gscratch, sizeof(double) * (ncc + nkc));
+    if (t->gscratch_bytes < dbl + u32) {
+      if (t->d_gscratch) (void)hipFree(t->d_gscratch);
+      t->d_gscratch = nullptr;
+      t->gscratch_bytes = 0;
+      const hipError_t ae = hipMalloc(&t->d_gscratch, dbl + u32);
       if (ae != hipSuccess) return hip_fail(ae, "hipMalloc(table-gradient scratch)");
+      t->gscratch_bytes = dbl + u32;
     }
-    a.g_cool_cells = (double*)t->d_gscratch;
-    a.g_coul_cells = a.g_cool_cells + ncc;
-    hipLaunchKernelGGL(k_zero, dim3(4096), dim3(256), 0, hs, a.g_cool_cells, ncc + nkc);
-  }
-  with_tab(t, [&](auto tab) {
-    if (a.o_tab)
+    double* d = (double*)t->d_gscratch;
+    a.g_cool_cells = d;
+    a.g_coul_cells = d + 16 * mc;
+    a.rec_cool = d + 16 * mc + 8 * mk;
+    a.rec_coul = a.rec_cool + 5 * nrec;
+    unsigned* u = (unsigned*)((char*)t->d_gscratch + dbl);
+    a.key_cool = u;
+    a.key_coul = u + nrec;
+    unsigned* order_cool = u + 2 * nrec;
+    unsigned* order_coul = u + 3 * nrec;
+    a.cnt_cool = u + 4 * nrec;
+    a.cnt_coul = a.cnt_cool + mc;
+    unsigned* start_cool = a.cnt_coul + mk;
+    unsigned* start_coul = start_cool + mc;
+    unsigned* cur_cool = start_coul + mk;
+    unsigned* cur_coul = cur_cool + mc;
+    unsigned* tmp_c = cur_coul + mk;
+    unsigned* tmp_k = tmp_c + sc_c;
+    hipLaunchKernelGGL(k_zero_u32, dim3(4096), dim3(256), 0, hs, a.cnt_cool, mc + mk);
+    with_tab(t, [&](auto tab) {
       hipLaunchKernelGGL((k_backward<decltype(tab), true>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, a, n);
-    else
-      hipLaunchKernelGGL((k_backward<decltype(tab), false>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, a, n);
-    return 0;
-  });
-  if (a.o_tab)
+      return 0;
+    });
+    scan_counts(a.cnt_cool, start_cool, mc, tmp_c, hs);
+    scan_counts(a.cnt_coul, start_coul, mk, tmp_k, hs);
+    hipError_t ce = hipMemcpyAsync(cur_cool, start_cool, sizeof(unsigned) * (mc + mk), hipMemcpyDeviceToDevice, hs);
+    if (ce != hipSuccess) return hip_fail(ce, "rc_cool_step_backward: cursor copy");
+    hipLaunchKernelGGL(k_order, dim3(4096), dim3(256), 0, hs, (const unsigned*)a.key_cool, cur_cool, order_cool, nrec);
+    hipLaunchKernelGGL(k_order, dim3(4096), dim3(256), 0, hs, (const unsigned*)a.key_coul, cur_coul, order_coul, nrec);
+    hipLaunchKernelGGL(k_gather_records<true>, dim3(4096), dim3(256), 0, hs, (const unsigned*)start_cool,
+                       (const unsigned*)a.cnt_cool, (const unsigned*)order_cool, (const double*)a.rec_cool,
+                       a.g_cool_cells, mc);
+    hipLaunchKernelGGL(k_gather_records<false>, dim3(4096), dim3(256), 0, hs, (const unsigned*)start_coul,
+                       (const unsigned*)a.cnt_coul, (const unsigned*)order_coul, (const double*)a.rec_coul,
+                       a.g_coul_cells, mk);
     hipLaunchKernelGGL(k_finish_cells, dim3(4096), dim3(256), 0, hs, a.o_tab, (const double*)a.g_cool_cells,
                        (const double*)a.g_coul_cells, ca.n[0], ca.n[1], ca.n[2], ka.n[0], ka.n[1], ka.n[2]);
+  } else {
+    with_tab(t, [&](auto tab) {
+      hipLaunchKernelGGL((k_backward<decltype(tab), false>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, a, n);
+      return 0;
+    });
+  }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "rc_cool_step_backward launch");
   return RC_OK;
@@ -252,6 +381,7 @@ extern "C" rc_status rc_selftest_backward_host(const rc_table_spec* spec, const 
   GlobalTab tab{cool.data(), stored.data() + 3 * vc, spec->cool.n[1], spec->cool.n[2], spec->coul.n[1],
                 spec->coul.n[2]};
   struct HostScatter {
+    enum { kRecords = 0 };
     double* g;
     long vc;
     void cool(const long* idx, const double* vb, const double* vse) const {

@@ -25,6 +25,8 @@ struct CoolPoint {
   double dyb[3], dyse[3];
   long idx[8];
   double w[8];
+  long cell;      // table cell (lowest corner) in cell numbering
+  double t[3];    // fractional coordinates inside it
 };
 
 struct CoulPoint {
@@ -32,6 +34,8 @@ struct CoulPoint {
   double dy[3];
   long idx[8];
   double w[8];
+  long cell;
+  double t[3];
 };
 
 template <class Tab>
@@ -61,6 +65,8 @@ RC_HD CoolPoint cool_point(const Tab& tab, const StepParams& P, double u0, doubl
       }
     }
   }
+  r.cell = ((long)c0.i * (n1 - 1) + c1.i) * (n2 - 1) + c2.i;
+  r.t[0] = c0.t; r.t[1] = c1.t; r.t[2] = c2.t;
   const double f0 = c0.i + c0.t, f1 = c1.i + c1.t, f2 = c2.i + c2.t;
   const double* cb = P.g->coef[0];
   const double* cs = P.g->coef[1];
@@ -96,6 +102,8 @@ RC_HD CoulPoint coul_point(const Tab& tab, const StepParams& P, double u0, doubl
       }
     }
   }
+  r.cell = ((long)c0.i * (n1 - 1) + c1.i) * (n2 - 1) + c2.i;
+  r.t[0] = c0.t; r.t[1] = c1.t; r.t[2] = c2.t;
   const double* co = P.g->coef[3];
   r.y = co[0] + co[1] * (c0.i + c0.t) + co[2] * (c1.i + c1.t) + co[3] * (c2.i + c2.t) + y;
   const double dfdu[3] = {c0.dfdu, c1.dfdu, c2.dfdu};
@@ -154,6 +162,9 @@ struct CellGrad {
 // the product v_synch v_eta, so their log2 entries receive identical
 // gradients and are scattered once; when the solution and the input state
 // fall in the same table cell their corner contributions are merged first.
+// A scatter with kRecords set receives instead one record per evaluation
+// point (sc.cool_rec / sc.coul_rec: table cell, coefficients, fractional
+// coordinates) for a later reduction by table cell.
 template <class Tab, class Scatter>
 RC_HD void cell_vjp(const Tab& tab, const StepParams& P, int c1, int c2, int k1, int k2, double n_e, double T_e,
                     double T_i, double B, double H, double floor_gas, double x, double z, unsigned char status,
@@ -236,41 +247,50 @@ RC_HD void cell_vjp(const Tab& tab, const StepParams& P, int c1, int c2, int k1,
   out->B = gB;
   out->H = gH;
   if (!want_tables) return;
-  // cooling tables
-  {
-    double vb[8], vse[8];
-    if (have[0] && have[1] && cp[0].idx[0] == cp[1].idx[0]) {
-      if (cb[0] != 0.0 || cse[0] != 0.0 || cb[1] != 0.0 || cse[1] != 0.0) {
-        for (int k = 0; k < 8; ++k) {
-          vb[k] = cb[0] * cp[0].w[k] + cb[1] * cp[1].w[k];
-          vse[k] = cse[0] * cp[0].w[k] + cse[1] * cp[1].w[k];
+  if constexpr (Scatter::kRecords != 0) {
+    // one record per evaluation point: its table cell, coefficients and
+    // fractional coordinates (the corner weights are rebuilt from them)
+    for (int p = 0; p < 2; ++p) {
+      if (have[p] && (cb[p] != 0.0 || cse[p] != 0.0)) sc.cool_rec(p, cp[p].cell, cb[p], cse[p], cp[p].t);
+      if (have[p] && cc[p] != 0.0) sc.coul_rec(p, kp[p].cell, cc[p], kp[p].t);
+    }
+  } else {
+    // cooling tables
+    {
+      double vb[8], vse[8];
+      if (have[0] && have[1] && cp[0].idx[0] == cp[1].idx[0]) {
+        if (cb[0] != 0.0 || cse[0] != 0.0 || cb[1] != 0.0 || cse[1] != 0.0) {
+          for (int k = 0; k < 8; ++k) {
+            vb[k] = cb[0] * cp[0].w[k] + cb[1] * cp[1].w[k];
+            vse[k] = cse[0] * cp[0].w[k] + cse[1] * cp[1].w[k];
+          }
+          sc.cool(cp[0].idx, vb, vse);
         }
-        sc.cool(cp[0].idx, vb, vse);
-      }
-    } else {
-      for (int p = 0; p < 2; ++p) {
-        if (!have[p] || (cb[p] == 0.0 && cse[p] == 0.0)) continue;
-        for (int k = 0; k < 8; ++k) {
-          vb[k] = cb[p] * cp[p].w[k];
-          vse[k] = cse[p] * cp[p].w[k];
+      } else {
+        for (int p = 0; p < 2; ++p) {
+          if (!have[p] || (cb[p] == 0.0 && cse[p] == 0.0)) continue;
+          for (int k = 0; k < 8; ++k) {
+            vb[k] = cb[p] * cp[p].w[k];
+            vse[k] = cse[p] * cp[p].w[k];
+          }
+          sc.cool(cp[p].idx, vb, vse);
         }
-        sc.cool(cp[p].idx, vb, vse);
       }
     }
-  }
-  // Coulomb table
-  {
-    double vc[8];
-    if (have[0] && have[1] && kp[0].idx[0] == kp[1].idx[0]) {
-      if (cc[0] != 0.0 || cc[1] != 0.0) {
-        for (int k = 0; k < 8; ++k) vc[k] = cc[0] * kp[0].w[k] + cc[1] * kp[1].w[k];
-        sc.coul(kp[0].idx, vc);
-      }
-    } else {
-      for (int p = 0; p < 2; ++p) {
-        if (!have[p] || cc[p] == 0.0) continue;
-        for (int k = 0; k < 8; ++k) vc[k] = cc[p] * kp[p].w[k];
-        sc.coul(kp[p].idx, vc);
+    // Coulomb table
+    {
+      double vc[8];
+      if (have[0] && have[1] && kp[0].idx[0] == kp[1].idx[0]) {
+        if (cc[0] != 0.0 || cc[1] != 0.0) {
+          for (int k = 0; k < 8; ++k) vc[k] = cc[0] * kp[0].w[k] + cc[1] * kp[1].w[k];
+          sc.coul(kp[0].idx, vc);
+        }
+      } else {
+        for (int p = 0; p < 2; ++p) {
+          if (!have[p] || cc[p] == 0.0) continue;
+          for (int k = 0; k < 8; ++k) vc[k] = cc[p] * kp[p].w[k];
+          sc.coul(kp[p].idx, vc);
+        }
       }
     }
   }

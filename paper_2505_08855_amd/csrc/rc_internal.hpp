@@ -29,7 +29,8 @@ struct rc_tables_s {
   rc::TableGeom geom{};             // axes and affine coefficients (host copy)
   rc::TableGeom* d_geom = nullptr;  // the same in device memory, read by the kernels
   void* d_counter = nullptr;        // work-queue counter of the batched kernel (allocated on first use)
-  void* d_gscratch = nullptr;       // backward: cell-blocked table-gradient accumulators (first use)
+  void* d_gscratch = nullptr;       // backward: table-gradient records and accumulators (first use)
+  size_t gscratch_bytes = 0;        // its size (grows with the cell count)
   // cell-blocked copies of the FP32 tables (RC_VARIANT_CELL; built on first use)
   void* d_cool_cells = nullptr;
   void* d_coul_cells = nullptr;
