@@ -279,9 +279,10 @@ typedef struct {
 /* Gradients written by the backward pass (device pointers).  The five
  * per-cell arrays (length n) are overwritten; NULL = not written.  tables
  * (n_values doubles, laid out as the residuals of rc_tables_import: gradient
- * with respect to each table's log2 node values) is accumulated (+=) with
- * device atomics, so its summation order, and the last bits of its values,
- * vary from run to run; NULL = not computed. */
+ * with respect to each table's log2 node values) is accumulated (+=); the
+ * per-cell contributions are grouped by table cell with integer atomics, so
+ * their summation order, and the last bits of the values, vary from run to
+ * run; NULL = not computed. */
 typedef struct {
   double* n_e;
   double* T_e;
@@ -298,8 +299,11 @@ typedef struct {
  * (on a floor-projected cell T_e' is constant).  The input-state rates Q_rad,
  * Q_cc add their direct derivatives.  RC_SCHEME_RATES is supported (T' = T);
  * RC_SCHEME_EXPLICIT16 gives RC_EUNSUPPORTED.  fwd must hold the outputs of a
- * forward call with the same tables, state, dt and options.  Asynchronous on
- * stream. */
+ * forward call with the same tables, state, dt and options.  With table
+ * gradients the call keeps device scratch in the table handle: two records
+ * per cell (about 160 bytes per cell) plus 24 doubles per table cell, allocated
+ * (hipMalloc) on the first call and whenever n grows past what it holds.
+ * Asynchronous on stream. */
 rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, int64_t n, double dt,
                                 const rc_step_opts* opts, const rc_fwd* fwd, const rc_cotangent* cot,
                                 const rc_grad* grad, void* stream);
