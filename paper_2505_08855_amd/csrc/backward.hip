@@ -61,6 +61,26 @@ struct AtomicScatter {
 // thread per table cell add up its records' corner contributions without
 // atomics on the gradients.  Record r = 2 i + p of cell i and point p; its key
 // is ~0u when the point contributes nothing.
+// Add 1 to cnt[key] for every active lane.  Neighbouring cells of coherent
+// inputs share table cells, and one atomic per lane on one counter serializes;
+// so the first kPeel distinct keys among the active lanes of the wavefront
+// take one atomic each, and the lanes left (independent inputs) one each.
+// The peel loop is uniform over the active lanes.
+constexpr int kPeel = 4;
+
+__device__ inline void wave_count(unsigned* cnt, unsigned key) {
+  const int lane = (int)(threadIdx.x & 63);
+  uint64_t todo = __ballot(1);
+  for (int it = 0; it < kPeel && todo; ++it) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const unsigned lk = __shfl(key, leader);
+    const uint64_t same = __ballot(key == lk) & todo;
+    if (lane == leader) atomicAdd(cnt + lk, (unsigned)__popcll(same));
+    todo &= ~same;
+  }
+  if ((todo >> lane) & 1ull) atomicAdd(cnt + key, 1u);
+}
+
 struct RecordScatter {
   enum { kRecords = 1 };
   unsigned* key_cool;
@@ -75,14 +95,14 @@ struct RecordScatter {
     double* q = rec_cool + r * 5;
     q[0] = cb; q[1] = cse; q[2] = t[0]; q[3] = t[1]; q[4] = t[2];
     key_cool[r] = (unsigned)cell;
-    atomicAdd(cnt_cool + cell, 1u);
+    wave_count(cnt_cool, (unsigned)cell);
   }
   __device__ void coul_rec(int p, long cell, double cc, const double* t) const {
     const long r = r0 + p;
     double* q = rec_coul + r * 4;
     q[0] = cc; q[1] = t[0]; q[2] = t[1]; q[3] = t[2];
     key_coul[r] = (unsigned)cell;
-    atomicAdd(cnt_coul + cell, 1u);
+    wave_count(cnt_coul, (unsigned)cell);
   }
 };
 
@@ -144,23 +164,46 @@ __global__ void k_scan_add(unsigned* out, const unsigned* offs, long n) {
     out[i] += offs[i / 1024];
 }
 
-// place record indices by table cell (cursor starts as the exclusive scan)
-__global__ void k_order(const unsigned* key, unsigned* cursor, unsigned* order, long nrec) {
-  for (long r = blockIdx.x * (long)blockDim.x + threadIdx.x; r < nrec; r += (long)gridDim.x * blockDim.x) {
-    const unsigned k = key[r];
-    if (k != ~0u) order[atomicAdd(cursor + k, 1u)] = (unsigned)r;
+// place record indices by table cell (cursor starts as the exclusive scan);
+// lanes of a wavefront with the same key take consecutive places from one atomic
+__global__ __launch_bounds__(256) void k_order(const unsigned* key, unsigned* cursor, unsigned* order, long nrec) {
+  const int lane = (int)(threadIdx.x & 63);
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // whole wavefronts step through the records so that every ballot is uniform
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long base = blockIdx.x * (long)blockDim.x; base < nrec; base += stride) {
+    const long r = base + threadIdx.x;
+    const unsigned k = r < nrec ? key[r] : ~0u;
+    uint64_t todo = __ballot(k != ~0u);
+    for (int it = 0; it < kPeel && todo; ++it) {
+      const int leader = __ffsll((unsigned long long)todo) - 1;
+      const unsigned lk = __shfl(k, leader);
+      const uint64_t same = __ballot(k == lk) & todo;
+      unsigned pos0 = 0;
+      if (lane == leader) pos0 = atomicAdd(cursor + lk, (unsigned)__popcll(same));
+      pos0 = __shfl(pos0, leader);
+      if ((same >> lane) & 1ull) order[pos0 + __popcll(same & below)] = (unsigned)r;
+      todo &= ~same;
+    }
+    if ((todo >> lane) & 1ull) order[atomicAdd(cursor + k, 1u)] = (unsigned)r;
   }
 }
 
+// table cells with more records than this are summed by k_gather_heavy
+constexpr unsigned kHeavy = 128;
+
 // one thread per table cell: the corner contributions of its records, written
-// to the cell-blocked gradient scratch (zero for a cell without records)
+// to the cell-blocked gradient scratch (zero for a cell without records, and
+// for a heavy cell, which k_gather_heavy then adds to)
 template <bool COOL>
 __global__ void k_gather_records(const unsigned* start, const unsigned* cnt, const unsigned* order,
-                                 const double* rec, double* cells, long ncell) {
+                                 const double* rec, double* cells, long ncell, unsigned* heavy, unsigned* nheavy) {
   for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < ncell; c += (long)gridDim.x * blockDim.x) {
     double acc0[8], acc1[8];
     for (int k = 0; k < 8; ++k) acc0[k] = acc1[k] = 0.0;
-    const unsigned b = start[c], m = cnt[c];
+    const bool is_heavy = cnt[c] > kHeavy;
+    if (is_heavy) heavy[atomicAdd(nheavy, 1u)] = (unsigned)c;
+    const unsigned b = start[c], m = is_heavy ? 0u : cnt[c];   // heavy cells: k_gather_heavy
     for (unsigned j = 0; j < m; ++j) {
       const double* q = rec + (long)order[b + j] * (COOL ? 5 : 4);
       const double c0 = q[0], c1 = COOL ? q[1] : 0.0;
@@ -179,6 +222,47 @@ __global__ void k_gather_records(const unsigned* start, const unsigned* cnt, con
     } else {
       for (int k = 0; k < 8; ++k) cells[c * 8 + k] = acc0[k];
     }
+  }
+}
+
+// heavy table cells (coherent inputs put many cells into one table cell):
+// one workgroup per heavy cell, its threads striding over the cell's records,
+// then a workgroup reduction and plain stores (no floating-point atomics)
+template <bool COOL>
+__global__ __launch_bounds__(256) void k_gather_heavy(const unsigned* start, const unsigned* cnt, const unsigned* order,
+                                                      const double* rec, double* cells, const unsigned* heavy,
+                                                      const unsigned* nheavy) {
+  constexpr int V = COOL ? 16 : 8;
+  __shared__ double red[V][256];
+  const unsigned nh = *nheavy;
+  for (unsigned h = blockIdx.x; h < nh; h += gridDim.x) {
+    const unsigned c = heavy[h];
+    const unsigned b = start[c], m = cnt[c];
+    double acc[V];
+    for (int v = 0; v < V; ++v) acc[v] = 0.0;
+    for (unsigned j = threadIdx.x; j < m; j += blockDim.x) {
+      const double* q = rec + (long)order[b + j] * (COOL ? 5 : 4);
+      const double c0 = q[0], c1 = COOL ? q[1] : 0.0;
+      const double t0 = q[COOL ? 2 : 1], t1 = q[COOL ? 3 : 2], t2 = q[COOL ? 4 : 3];
+      for (int k = 0; k < 8; ++k) {
+        const double w = ((k >> 2) ? t0 : 1.0 - t0) * (((k >> 1) & 1) ? t1 : 1.0 - t1) * ((k & 1) ? t2 : 1.0 - t2);
+        if (COOL) {
+          acc[2 * k] += c0 * w;
+          acc[2 * k + 1] += c1 * w;
+        } else {
+          acc[k] += c0 * w;
+        }
+      }
+    }
+    for (int v = 0; v < V; ++v) red[v][threadIdx.x] = acc[v];
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+      if ((int)threadIdx.x < d)
+        for (int v = 0; v < V; ++v) red[v][threadIdx.x] += red[v][threadIdx.x + d];
+      __syncthreads();
+    }
+    if ((int)threadIdx.x < V) cells[(long)c * V + threadIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
   }
 }
 
@@ -295,7 +379,7 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
   // uint32: keys, orders (2 x nrec each), counts, starts, cursors (3 x (mc + mk)), scan sums
   const long sc_c = 2 * ((mc + 1023) / 1024) + 2, sc_k = 2 * ((mk + 1023) / 1024) + 2;
   const size_t dbl = sizeof(double) * (size_t)(16 * mc + 8 * mk + 9 * nrec);
-  const size_t u32 = sizeof(unsigned) * (size_t)(4 * nrec + 3 * (mc + mk) + sc_c + sc_k);
+  const size_t u32 = sizeof(unsigned) * (size_t)(4 * nrec + 4 * (mc + mk) + sc_c + sc_k + 2);
   if (a.o_tab) {
     if (t->gscratch_bytes < dbl + u32) {
       if (t->d_gscratch) (void)hipFree(t->d_gscratch);
@@ -323,7 +407,11 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
     unsigned* cur_coul = cur_cool + mc;
     unsigned* tmp_c = cur_coul + mk;
     unsigned* tmp_k = tmp_c + sc_c;
+    unsigned* heavy_cool = tmp_k + sc_k;
+    unsigned* heavy_coul = heavy_cool + mc;
+    unsigned* nheavy = heavy_coul + mk;   // [cooling, Coulomb]
     hipLaunchKernelGGL(k_zero_u32, dim3(4096), dim3(256), 0, hs, a.cnt_cool, mc + mk);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, hs, nheavy, 2L);
     with_tab(t, [&](auto tab) {
       hipLaunchKernelGGL((k_backward<decltype(tab), true>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, a, n);
       return 0;
@@ -336,10 +424,16 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
     hipLaunchKernelGGL(k_order, dim3(4096), dim3(256), 0, hs, (const unsigned*)a.key_coul, cur_coul, order_coul, nrec);
     hipLaunchKernelGGL(k_gather_records<true>, dim3(4096), dim3(256), 0, hs, (const unsigned*)start_cool,
                        (const unsigned*)a.cnt_cool, (const unsigned*)order_cool, (const double*)a.rec_cool,
-                       a.g_cool_cells, mc);
+                       a.g_cool_cells, mc, heavy_cool, nheavy);
     hipLaunchKernelGGL(k_gather_records<false>, dim3(4096), dim3(256), 0, hs, (const unsigned*)start_coul,
                        (const unsigned*)a.cnt_coul, (const unsigned*)order_coul, (const double*)a.rec_coul,
-                       a.g_coul_cells, mk);
+                       a.g_coul_cells, mk, heavy_coul, nheavy + 1);
+    hipLaunchKernelGGL(k_gather_heavy<true>, dim3(1024), dim3(256), 0, hs, (const unsigned*)start_cool,
+                       (const unsigned*)a.cnt_cool, (const unsigned*)order_cool, (const double*)a.rec_cool,
+                       a.g_cool_cells, (const unsigned*)heavy_cool, (const unsigned*)nheavy);
+    hipLaunchKernelGGL(k_gather_heavy<false>, dim3(1024), dim3(256), 0, hs, (const unsigned*)start_coul,
+                       (const unsigned*)a.cnt_coul, (const unsigned*)order_coul, (const double*)a.rec_coul,
+                       a.g_coul_cells, (const unsigned*)heavy_coul, (const unsigned*)(nheavy + 1));
     hipLaunchKernelGGL(k_finish_cells, dim3(4096), dim3(256), 0, hs, a.o_tab, (const double*)a.g_cool_cells,
                        (const double*)a.g_coul_cells, ca.n[0], ca.n[1], ca.n[2], ka.n[0], ka.n[1], ka.n[2]);
   } else {
