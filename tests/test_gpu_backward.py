@@ -106,3 +106,50 @@ def test_backward_rates_scheme_and_errors(dev, imported):
         R.cool_step_backward(gt, st, DT, None, {}, R.default_opts(scheme="explicit16"))
     with pytest.raises(R.RadcoolError):
         R.cool_step_backward(gt, st, DT, None, {})      # Newton needs the forward outputs
+
+
+@pytest.fixture(scope="module")
+def storage(tables64):
+    co, re, _ = T.quantize_tables(tables64)
+    return (np.concatenate([re[k].ravel() for k in T.TABLE_NAMES]), np.stack([co[k] for k in T.TABLE_NAMES]))
+
+
+def _table_grad_gpu_vs_host(dev, gt, storage, cells, cot_seed):
+    """Table gradient of the GPU adjoint (records sorted by table cell) against
+    the same per-cell code on the host with plain accumulation."""
+    n = cells["n_e"].size
+    st = {k: to_dev(cells[k], dev) for k in W.FIELDS}
+    fwd = R.cool_step(gt, st, DT)
+    rng = np.random.default_rng(cot_seed)
+    cot = {k: rng.normal(size=n) for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")}
+    _, nv = gt.info()
+    tg = torch.zeros(nv, dtype=torch.float64, device=dev)
+    g = R.cool_step_backward(gt, st, DT, fwd, {k: to_dev(v, dev) for k, v in cot.items()}, table_grad=tg)
+    fwd_np = {k: fwd[k].cpu().numpy() for k in ("T_e_new", "T_i_new", "status")}
+    hg, htab = R.selftest_backward_host(R.default_spec(64), storage[0], storage[1], cells, fwd_np, cot, DT)
+    got = tg.cpu().numpy()
+    scale = np.max(np.abs(htab)) if htab.size else 1.0
+    assert np.max(np.abs(got - htab)) <= 1e-11 * scale
+    out = {k: fwd[k].cpu().numpy() for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")}
+    mag = sum(np.abs(cot[k] * out[k]) for k in out)
+    for f in W.FIELDS:
+        a, b = g[f].cpu().numpy(), hg[f]
+        ok = np.isfinite(b) & np.isfinite(mag)
+        # same per-cell code, contractions may differ: rounding relative to the
+        # sizes of the terms that make up the gradient (as against the oracle)
+        err = np.abs(a[ok] - b[ok]) * cells[f][ok]
+        assert np.all(err <= 1e-9 * np.abs(b[ok] * cells[f][ok]) + 1e-12 * mag[ok]), f
+
+
+def test_table_gradient_records_coherent_and_ragged(dev, imported, storage):
+    """The record path on coherent cells (many cells per table cell: the
+    crowded-cell reduction), on independent cells with invalid ones and a
+    ragged count, and on successive calls of decreasing size (scratch reuse)."""
+    gt, _ = imported
+    _table_grad_gpu_vs_host(dev, gt, storage, W.sphere_cells(n_r=8, n_th=8, n_ph=256), 1)
+    cells = W.workload(3, n=1001)
+    cells["T_e"][[3, 500]] = np.nan
+    _table_grad_gpu_vs_host(dev, gt, storage, cells, 2)
+    _table_grad_gpu_vs_host(dev, gt, storage, W.workload(0, n=5000), 3)
+    _table_grad_gpu_vs_host(dev, gt, storage, W.workload(0, n=300), 4)
+    _table_grad_gpu_vs_host(dev, gt, storage, W.workload(0, n=1), 5)
