@@ -302,8 +302,9 @@ typedef struct {
  * forward call with the same tables, state, dt and options.  With table
  * gradients the call keeps device scratch in the table handle: two records
  * per cell (about 160 bytes per cell) plus 24 doubles per table cell, allocated
- * (hipMalloc) on the first call and whenever n grows past what it holds.
- * Asynchronous on stream. */
+ * (hipMalloc) on the first call and whenever n grows past what it holds;
+ * backward calls with table gradients that overlap on one table handle must
+ * therefore use the same stream.  Asynchronous on stream. */
 rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, int64_t n, double dt,
                                 const rc_step_opts* opts, const rc_fwd* fwd, const rc_cotangent* cot,
                                 const rc_grad* grad, void* stream);

@@ -17,11 +17,15 @@
 //   driven to zero by Newton in s = ln x on
 //     G(s) = log1p([c (x - T_e) + c (z - T_i) + dt Q_rad(x)] / (c (T_e + T_i))),
 //   whose slope uses dz/dx = -(dE2/dx)/(dE2/dz) (the off-diagonal Jacobian
-//   blocks).  On cooling iterates away from x = T_e the step is instead
-//   Newton's on the log-log form ln(dt Q_rad) - ln(c (T_e - x) + c (T_i - z)),
-//   which has the same sign and converges faster for strong cooling.  Every
-//   derivative is the exact derivative of the interpolant inside the current
-//   table cell.  The iteration starts at x = T_e, moves in
+//   blocks).  Each iterate also takes Newton's step on the log-ratio form
+//   ln(energy gained) - ln(energy lost) of the electron-ion pair, which has
+//   the sign of G, and of the two steps the one that overshoots less is taken
+//   (cooling residuals are convex in s, heating ones concave); a long first
+//   step goes to the root of a model of the cell instead.  Every derivative is
+//   the exact derivative of the interpolant inside the current table cell.  A
+//   step below sqrt(tol) that stays in the current cells ends the solve, T_i'
+//   following by first-order extrapolation along z(x).  The iteration starts
+//   at x = T_e, moves in
 //   the direction the source points and keeps a sign bracket, so it lands on
 //   the first root met from the initial state; when the step would cross the
 //   temperature floor it probes G at the floor and projects onto it if the
