@@ -177,10 +177,10 @@ def parse():
 def cells_for(name):
     from paper_2505_08855_amd import workloads as W
     if name == "iid256":
-        return W.workload(1), "iid cells 256^3 (n_e, T_e, T_i, B, H FP64 SoA), tables 4x128^3 FP32"
+        return W.workload(1), "iid cells 256^3 (n_e, T_e, T_i, B, H FP64 SoA), tables 4x128^3 FP32 read through their cell-blocked copy"
     if name == "iid32":
-        return W.workload(0), "iid cells 32^3, tables 4x64^3 FP32"
-    return W.workload(2), "spherical-polar MAD-like profile 128^3, tables 4x64^3 FP32"
+        return W.workload(0), "iid cells 32^3, tables 4x64^3 FP32 (cell-blocked copy)"
+    return W.workload(2), "spherical-polar MAD-like profile 128^3, tables 4x64^3 FP32 (cell-blocked copy)"
 
 
 def time_steps(R, torch, tables, state, dt, opts, out, steps, warmup):
@@ -257,7 +257,7 @@ def bench_blocks(args, R, W, torch, dev):
            "value": n / (ms * 1e-3) / 1e9, "unit": "Gcell-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "4096 AMR blocks (8^3..32^3, mixed) x 8 accretion states, tables 4x64^3 FP32, "
+           "config": {"workload": "4096 AMR blocks (8^3..32^3, mixed) x 8 accretion states, tables 4x64^3 FP32 (cell-blocked copy), "
                                   "one captured persistent launch", "cells": n, "blocks": nb,
                       "scheme": args.scheme, "plan": plan.info()},
            "roofline": {"bound": "hbm", "achieved": algo / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
