@@ -31,8 +31,6 @@ def build(verbose=False, extra_flags=()):
     cmd = [hipcc(), "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-command-line-argument",
-           # native FP64 atomic add for the table-gradient scatter (coarse-grained device memory)
-           "-munsafe-fp-atomics",
            "-I", INCLUDE, "-I", CSRC]
     cmd += list(extra_flags)
     cmd += [os.path.join(CSRC, s) for s in SOURCES]

@@ -1,10 +1,15 @@
 // Adjoint kernel and the rc_cool_step_backward entry point.
 //
 // One thread per cell: recompute the interpolant pieces at the forward
-// solution and at the input state, solve the transposed 2x2 system, write the
-// five input gradients (coalesced) and scatter the table-entry gradients with
-// FP64 atomics (native global_atomic_add_f64 on gfx950; the buffers are
-// coarse-grained device memory).
+// solution and at the input state, solve the transposed 2x2 system and write
+// the five input gradients (coalesced).  Table-entry gradients, when asked
+// for, take no floating-point atomics: every cell writes one record per
+// evaluation point (its table cell, coefficients and fractional coordinates),
+// a counting sort groups the records by table cell (integer atomics on the
+// counts and placement cursors, aggregated per wavefront), one thread per
+// table cell (one workgroup for a crowded one) adds up its records' corner
+// contributions into cell-blocked scratch, and a last pass folds the cells
+// onto the table nodes.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -24,7 +29,6 @@ struct BwdArgs {
   const uint8_t* status;
   const double *g_x, *g_z, *g_qr, *g_qc;
   double *o_n, *o_Te, *o_Ti, *o_B, *o_H, *o_tab;
-  double* g_se;           // scratch: gradient shared by the synch and eta entries
   double* g_cool_cells;   // scratch, cell-blocked: {brem, synch * eta} per corner of each cooling cell
   double* g_coul_cells;   // scratch, cell-blocked: one value per corner of each Coulomb cell
   unsigned *key_cool, *key_coul, *cnt_cool, *cnt_coul;   // gradient records (see RecordScatter)
@@ -34,24 +38,12 @@ struct BwdArgs {
   int newton;
 };
 
-// Table-gradient scatter with device atomics: brem and Coulomb straight into
-// the caller's array, the shared synch * eta gradient into library scratch
-// (added to both tables' slots by k_finish_se).
-struct AtomicScatter {
+// The adjoint without table gradients: cell_vjp is called with want_tables
+// false, so nothing reaches the scatter.
+struct NoScatter {
   enum { kRecords = 0 };
-  double* g_brem;
-  double* g_coul;
-  double* g_se;
-  __device__ void cool(const long* idx, const double* vb, const double* vse) const {
-    for (int k = 0; k < 8; ++k) {
-      if (vb[k] != 0.0) atomicAdd(g_brem + idx[k], vb[k]);
-      if (vse[k] != 0.0) atomicAdd(g_se + idx[k], vse[k]);
-    }
-  }
-  __device__ void coul(const long* idx, const double* vc) const {
-    for (int k = 0; k < 8; ++k)
-      if (vc[k] != 0.0) atomicAdd(g_coul + idx[k], vc[k]);
-  }
+  __device__ void cool(const long*, const double*, const double*) const {}
+  __device__ void coul(const long*, const double*) const {}
 };
 
 // Table-gradient records: the adjoint writes, per cell and evaluation point,
@@ -110,14 +102,12 @@ template <class Tab, bool CELLS>
 __global__ __launch_bounds__(256, 2) void k_backward(Tab tab, StepParams P, BwdArgs a, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  using Scatter = typename std::conditional<CELLS, RecordScatter, AtomicScatter>::type;
+  using Scatter = typename std::conditional<CELLS, RecordScatter, NoScatter>::type;
   Scatter sc;
   if constexpr (CELLS) {
     sc = RecordScatter{a.key_cool, a.rec_cool, a.cnt_cool, a.key_coul, a.rec_coul, a.cnt_coul, 2 * i};
     a.key_cool[2 * i] = a.key_cool[2 * i + 1] = ~0u;
     a.key_coul[2 * i] = a.key_coul[2 * i + 1] = ~0u;
-  } else {
-    sc = AtomicScatter{a.o_tab, a.o_tab ? a.o_tab + 3 * a.vc : nullptr, a.g_se};
   }
   CellGrad g;
   const double x = a.newton ? a.x[i] : a.T_e[i];
@@ -132,10 +122,6 @@ __global__ __launch_bounds__(256, 2) void k_backward(Tab tab, StepParams P, BwdA
   if (a.o_Ti) a.o_Ti[i] = g.T_i;
   if (a.o_B) a.o_B[i] = g.B;
   if (a.o_H) a.o_H[i] = g.H;
-}
-
-__global__ void k_zero(double* p, long n) {
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0.0;
 }
 
 __global__ void k_zero_u32(unsigned* p, long n) {
@@ -300,15 +286,6 @@ __global__ void k_finish_cells(double* g_tab, const double* cool_cells, const do
   }
 }
 
-// add the shared synch * eta gradient to both tables' slots
-__global__ void k_finish_se(double* g_tab, const double* g_se, long vc) {
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < vc; i += (long)gridDim.x * blockDim.x) {
-    const double v = g_se[i];
-    g_tab[vc + i] += v;
-    g_tab[2 * vc + i] += v;
-  }
-}
-
 // exclusive scan of m counts into out; tmp holds the chunk sums of every
 // level (at most 2 ceil(m / 1024) + 2 entries)
 void scan_counts(const unsigned* in, unsigned* out, long m, unsigned* tmp, hipStream_t hs) {
@@ -366,7 +343,6 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
   const int64_t grid = (n + block - 1) / block;
   if (grid > 0x7fffffffLL) return set_error(RC_EINVAL, "rc_cool_step_backward: n too large for one launch");
   hipStream_t hs = (hipStream_t)stream;
-  a.g_se = nullptr;
   a.g_cool_cells = a.g_coul_cells = nullptr;
   a.key_cool = a.key_coul = a.cnt_cool = a.cnt_coul = nullptr;
   a.rec_cool = a.rec_coul = nullptr;

@@ -302,8 +302,8 @@ def test_newton_launch_shapes_agree(dev, imported64, n, dt_scale):
 @pytest.mark.parametrize("block", [0, 256])
 def test_gas_floor_energy_tier(dev, imported64, spec64, block):
     """Per-cell gas-temperature floor: cells below it take the step with
-    radiative cooling off (status 32), through the deferred launches and the
-    plain kernel."""
+    radiative cooling off (status 32), with one-wavefront and 256-thread
+    workgroups."""
     from oracle import upstream as U
     gt, stored = imported64
     cells = W.workload(0)
