@@ -163,6 +163,7 @@ def parse():
     p.add_argument("--table-n", type=int, default=128)
     p.add_argument("--variant", default="auto")
     p.add_argument("--scheme", default="newton")
+    p.add_argument("--passes", type=int, default=0, help="Newton step passes (0 = library choice, 1, 2)")
     p.add_argument("--sample", type=int, default=131072, help="cells in the cpu_baseline sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-variants", action="store_true")
@@ -364,7 +365,7 @@ def main():
     t_build = time.perf_counter() - t0
     out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")}
     out["status"] = torch.empty(n, dtype=torch.uint8, device=dev)
-    opts = R.default_opts(variant=args.variant, scheme=args.scheme)
+    opts = R.default_opts(variant=args.variant, scheme=args.scheme, passes=args.passes)
     ms, wall = time_steps(R, torch, tables, state, dt, opts, out, args.steps, args.warmup)
     table_bytes = 4 * 4 * table_n ** 3
     algo_bytes = BYTES_PER_CELL * n + table_bytes

@@ -162,6 +162,19 @@ typedef struct {
   double T_floor;        /* K, cooling is zero below it (Sec. III.B.2; default 1e6) */
   double tol;            /* target relative accuracy of T_e' (default 1e-12): a Newton step
                             below sqrt(tol) in ln T_e' ends the solve */
+  int32_t passes;        /* Newton scheme, variants AUTO, CELL and GLOBAL: 0 = library
+                            choice (2), 1 = one kernel, every cell solved by its own
+                            thread in cell order; 2 = two passes: every cell's first
+                            Newton round in cell order, then the unfinished cells,
+                            grouped per tile of 4096 cells by the length of their
+                            first proposed step, resumed so that the cells of a
+                            wavefront need similar numbers of rounds.  Identical
+                            results; two passes keep device scratch in the table
+                            handle (59 bytes per cell, allocated (hipMalloc) on the
+                            first call and whenever n grows past what it holds), so
+                            two-pass calls that overlap on one table handle must use
+                            the same stream.  Ignored by other schemes and variants. */
+  int32_t reserved;      /* must be 0 */
 } rc_step_opts;
 
 /* Fill *spec with the default axes (n points per axis):
@@ -171,7 +184,7 @@ typedef struct {
 rc_status rc_default_spec(rc_table_spec* spec, int32_t n);
 
 /* Fill *opts with: Newton scheme, AUTO variant, max_iter 60, block 0,
- * T_floor 1e6 K, tol 1e-12. */
+ * T_floor 1e6 K, tol 1e-12, passes 0. */
 rc_status rc_default_opts(rc_step_opts* opts);
 
 /* Build the four tables on the current device from the closed forms of Sec. II

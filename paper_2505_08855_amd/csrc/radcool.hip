@@ -91,6 +91,8 @@ extern "C" rc_status rc_default_opts(rc_step_opts* o) {
   o->block = 0;
   o->T_floor = 1.0e6;
   o->tol = 1.0e-12;
+  o->passes = 0;
+  o->reserved = 0;
   return RC_OK;
 }
 
@@ -277,6 +279,7 @@ void destroy_tables(rc_tables_s* t) {
   if (t->d_coul) (void)hipFree(t->d_coul);
   if (t->d_counter) (void)hipFree(t->d_counter);
   if (t->d_gscratch) (void)hipFree(t->d_gscratch);
+  if (t->d_step_scratch) (void)hipFree(t->d_step_scratch);
   if (t->d_cool_cells) (void)hipFree(t->d_cool_cells);
   if (t->d_coul_cells) (void)hipFree(t->d_coul_cells);
   t->magic = 0;
@@ -584,6 +587,25 @@ extern "C" rc_status rc_selftest_step_host(const rc_table_spec* spec, const floa
     CellOut o;
     if (opts->variant == RC_VARIANT_DIRECT) {
       direct_rates(P, n_e[i], T_e[i], T_i[i], B[i], H[i], T_floor_gas ? T_floor_gas[i] : 0.0, &o);
+    } else if (opts->scheme == RC_SCHEME_NEWTON && opts->passes == 2 && !bad_input(n_e[i]) && !bad_input(T_e[i]) &&
+               !bad_input(T_i[i]) && !bad_input(B[i]) && !bad_input(H[i])) {
+      // the two-pass step's per-cell path: the first round, the resume
+      // record, then a fresh solver resuming from it (the device passes)
+      CellSolver<GlobalTab> first(tab, P);
+      const double s0 = first.setup(n_e[i], T_e[i], T_i[i], B[i], H[i], dt, T_floor_gas ? T_floor_gas[i] : 0.0);
+      o.status = first.clamp;
+      NewtonState ns;
+      first.newton_begin(s0, ns);
+      if (!first.newton_round(ns, &o)) {
+        NewtonResume rec;
+        CellSolver<GlobalTab>::save_resume(ns, &rec);
+        CellSolver<GlobalTab> second(tab, P);
+        const double s1 = second.setup(n_e[i], T_e[i], T_i[i], B[i], H[i], dt, T_floor_gas ? T_floor_gas[i] : 0.0);
+        NewtonState ns2;
+        second.load_resume(s1, rec, ns2);
+        while (!second.newton_round(ns2, &o)) {
+        }
+      }
     } else {
       cool_cell_any(tab, P, n_e[i], T_e[i], T_i[i], B[i], H[i], T_floor_gas ? T_floor_gas[i] : 0.0, false, &o);
     }

@@ -31,6 +31,8 @@ struct rc_tables_s {
   void* d_counter = nullptr;        // work-queue counter of the batched kernel (allocated on first use)
   void* d_gscratch = nullptr;       // backward: table-gradient records and accumulators (first use)
   size_t gscratch_bytes = 0;        // its size (grows with the cell count)
+  void* d_step_scratch = nullptr;   // two-pass Newton step: resume records, classes, tile lists (first use)
+  size_t step_scratch_bytes = 0;    // its size (grows with the cell count)
   // cell-blocked copies of the FP32 tables (RC_VARIANT_CELL; built on first use)
   void* d_cool_cells = nullptr;
   void* d_coul_cells = nullptr;

@@ -190,6 +190,20 @@ struct NewtonState {
   int kind, iters, flags;
 };
 
+// The part of NewtonState a cell still needs after its first round when that
+// round did not finish it: the first round leaves the iterate at s0 = ln T_e,
+// z_floor at T_i and the round count at 0, and the pending point's
+// temperature follows from se and the kind, so 56 bytes resume the solve
+// exactly where it stopped.
+struct NewtonResume {
+  double G, dG, z, lo, hi, se;
+  int kind_flags;       // kind | flags << 3
+  int pad;
+};
+
+// Number of difficulty classes of unfinished cells (see CellSolver::resume_class).
+constexpr int kResumeClasses = 16;
+
 // the table coordinates that stay fixed during a cell's solve: N and B of the
 // cooling tables, n_e of the Coulomb table
 struct FixedCoords {
@@ -647,6 +661,39 @@ struct CellSolver {
     newton_begin(s0, ns);
     while (!newton_round(ns, o)) {
     }
+  }
+
+  // state of a cell that its first round left unfinished
+  RC_HD static void save_resume(const NewtonState& ns, NewtonResume* r) {
+    r->G = ns.G; r->dG = ns.dG; r->z = ns.z; r->lo = ns.lo; r->hi = ns.hi; r->se = ns.se;
+    r->kind_flags = ns.kind | (ns.flags << 3);
+    r->pad = 0;
+  }
+
+  // the NewtonState save_resume came from (setup() of the same cell has run)
+  RC_HD void load_resume(double s0, const NewtonResume& r, NewtonState& ns) const {
+    ns.s = s0; ns.G = r.G; ns.dG = r.dG; ns.z = r.z; ns.lo = r.lo; ns.hi = r.hi; ns.se = r.se;
+    ns.kind = r.kind_flags & 7;
+    ns.flags = r.kind_flags >> 3;
+    ns.iters = 0;
+    ns.z_floor = T_i;
+    // the pending point: exp(se) for an iterate (computed the same way when
+    // it was proposed), the floor for a floor probe
+    ns.xe = ns.kind == ITER ? fexp(ns.se) : Tf();
+  }
+
+  // Difficulty class of a cell after an unfinished first round, for grouping
+  // cells that need similar numbers of further rounds: half-decade bins of
+  // the first proposed step |se - s0| in ln T_e, from below 1e-6 (class 0) to
+  // above 10^0.5 (class 14); class 15 for a floor probe.  The further round
+  // count grows with that step (Newton from a model root: a short first step
+  // converges in one more round, a step of order one takes three).
+  RC_HD static int resume_class(const NewtonState& ns) {
+    if (ns.kind != ITER) return kResumeClasses - 1;
+    const float d = (float)fabs(ns.se - ns.s);
+    const float l = flog2_sp(d > 1e-30f ? d : 1e-30f) * 0.30103f;   // log10
+    const int k = (int)floorf(2.0f * (l + 6.0f));
+    return k < 0 ? 0 : (k > kResumeClasses - 2 ? kResumeClasses - 2 : k);
   }
 
   RC_HD void explicit16(double s0, CellOut* o) {

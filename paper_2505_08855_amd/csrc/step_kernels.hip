@@ -113,12 +113,161 @@ __global__ __launch_bounds__(256, kStepWaves<SCHEME>) void k_step_lds(Base base,
   store(o, i, r);
 }
 
+// ------------------------------------------------------------------ two-pass Newton step
+//
+// A wavefront runs as many Newton rounds as its slowest lane, and on
+// independent cells the per-cell round count spreads from 1 to 5 (mean 2.3,
+// wavefront maximum 4.6 on the iid workload).  The two-pass step regroups the
+// work: pass 1 runs every cell's first round (the rates at the input state,
+// the first residual, the first proposed step) in cell order and writes out
+// the cells it finished; the others leave a 56-byte resume record and a
+// difficulty class (the length of the proposed step, which predicts the
+// further round count).  A counting sort per tile of kTile cells orders each
+// tile's unfinished cells by class, and pass 2 resumes them in that order, so
+// that the lanes of a wavefront need similar numbers of further rounds.  The
+// per-cell arithmetic is the single-pass kernel's: results are identical.
+
+constexpr int kTile = 4096;                 // cells per sort tile
+constexpr uint8_t kClassDone = 0xff;        // class of a cell finished in pass 1
+
+struct ResumeArgs {
+  NewtonResume* rec;    // per cell: resume record (unfinished cells only)
+  uint8_t* cls;         // per cell: difficulty class, kClassDone when finished
+  uint16_t* list;       // per tile: tile-local indices of unfinished cells, by class
+  unsigned* count;      // per tile: number of unfinished cells
+  int64_t ntiles;
+};
+
+template <class Tab>
+__global__ __launch_bounds__(256, RC_NEWTON_WAVES) void k_newton_first(Tab tab, StepParams P, StateArgs s, OutArgs o,
+                                                                     ResumeArgs ra, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double n_e = s.n_e[i], T_e = s.T_e[i], T_i = s.T_i[i], B = s.B[i], H = s.H[i];
+  const bool diag = o.Q_brem || o.Q_syn || o.eta;
+  CellOut r;
+  if (bad_input(n_e) || bad_input(T_e) || bad_input(T_i) || bad_input(B) || bad_input(H)) {
+    const double nan = __builtin_nan("");
+    r.T_e_new = r.T_i_new = r.q_rad = r.q_cc = r.q_brem = r.q_syn = r.eta = nan;
+    r.status = ST_INVALID;
+    store(o, i, r);
+    ra.cls[i] = kClassDone;
+    return;
+  }
+  CellSolver<Tab> cs(tab, P);
+  const double s0 = cs.setup(n_e, T_e, T_i, B, H, P.dt, floor_gas_at(s, i));
+  r.status = cs.clamp;
+  NewtonState ns;
+  cs.newton_begin(s0, ns);
+  const bool done = cs.newton_round(ns, &r);
+  if (diag) cs.diagnostics(s0, &r);
+  if (o.Q_rad) o.Q_rad[i] = r.q_rad;
+  if (o.Q_cc) o.Q_cc[i] = r.q_cc;
+  if (o.Q_brem) o.Q_brem[i] = r.q_brem;
+  if (o.Q_syn) o.Q_syn[i] = r.q_syn;
+  if (o.eta) o.eta[i] = r.eta;
+  if (done) {
+    if (o.T_e_new) o.T_e_new[i] = r.T_e_new;
+    if (o.T_i_new) o.T_i_new[i] = r.T_i_new;
+    if (o.status) o.status[i] = r.status;
+    ra.cls[i] = kClassDone;
+  } else {
+    CellSolver<Tab>::save_resume(ns, &ra.rec[i]);
+    ra.cls[i] = (uint8_t)CellSolver<Tab>::resume_class(ns);
+  }
+}
+
+// one workgroup per tile: counting sort of the tile's unfinished cells by class
+__global__ __launch_bounds__(256) void k_tile_sort(ResumeArgs ra, int64_t n) {
+  __shared__ unsigned hist[kResumeClasses];
+  constexpr int kPer = kTile / 256;
+  const int tid = (int)threadIdx.x;
+  const int64_t base = blockIdx.x * (int64_t)kTile;
+  const int m = (int)(n - base < kTile ? n - base : kTile);
+  if (tid < kResumeClasses) hist[tid] = 0u;
+  __syncthreads();
+  uint8_t c[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int j = tid + 256 * k;
+    c[k] = j < m ? ra.cls[base + j] : kClassDone;
+    if (c[k] != kClassDone) atomicAdd(&hist[c[k]], 1u);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned acc = 0;
+    for (int k = 0; k < kResumeClasses; ++k) {
+      const unsigned h = hist[k];
+      hist[k] = acc;
+      acc += h;
+    }
+    ra.count[blockIdx.x] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (c[k] != kClassDone) ra.list[base + atomicAdd(&hist[c[k]], 1u)] = (uint16_t)(tid + 256 * k);
+}
+
+// Pass 2: one wavefront per 64 sorted cells of a tile.  Workgroups are dealt
+// to the 8 XCDs round-robin, so the mapping below puts all chunks of a tile on
+// one XCD, consecutively: the tile's state and records are fetched into one L2.
+template <class Tab>
+__global__ __launch_bounds__(64, RC_NEWTON_WAVES) void k_newton_resume(Tab tab, StepParams P, StateArgs s, OutArgs o,
+                                                                     ResumeArgs ra) {
+  const int64_t b = blockIdx.x;
+  const int64_t slot = b >> 3;
+  const int64_t tile = (slot / (kTile / 64)) * 8 + (b & 7);
+  const unsigned chunk = (unsigned)(slot % (kTile / 64));
+  if (tile >= ra.ntiles) return;
+  const unsigned j = chunk * 64u + threadIdx.x;
+  if (j >= ra.count[tile]) return;
+  const int64_t i = tile * kTile + ra.list[tile * kTile + j];
+  CellSolver<Tab> cs(tab, P);
+  const double s0 = cs.setup(s.n_e[i], s.T_e[i], s.T_i[i], s.B[i], s.H[i], P.dt, floor_gas_at(s, i));
+  CellOut r;
+  r.status = cs.clamp;
+  NewtonState ns;
+  cs.load_resume(s0, ra.rec[i], ns);
+  while (!cs.newton_round(ns, &r)) {
+  }
+  if (o.T_e_new) o.T_e_new[i] = r.T_e_new;
+  if (o.T_i_new) o.T_i_new[i] = r.T_i_new;
+  if (o.status) o.status[i] = r.status;
+}
+
 __global__ __launch_bounds__(256) void k_direct(StepParams P, StateArgs s, OutArgs o, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   CellOut r;
   direct_rates(P, s.n_e[i], s.T_e[i], s.T_i[i], s.B[i], s.H[i], floor_gas_at(s, i), &r);
   store(o, i, r);
+}
+
+// the two-pass step's scratch in the table handle, grown to hold n cells
+rc_status step_scratch(rc_tables_s* t, int64_t n, ResumeArgs* ra) {
+  const int64_t ntiles = (n + kTile - 1) / kTile;
+  const auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t b_rec = up(sizeof(NewtonResume) * (size_t)n);
+  const size_t b_cls = up((size_t)n);
+  const size_t b_list = up(sizeof(uint16_t) * (size_t)ntiles * kTile);
+  const size_t b_cnt = up(sizeof(unsigned) * (size_t)ntiles);
+  const size_t need = b_rec + b_cls + b_list + b_cnt;
+  if (t->step_scratch_bytes < need) {
+    if (t->d_step_scratch) (void)hipFree(t->d_step_scratch);
+    t->d_step_scratch = nullptr;
+    t->step_scratch_bytes = 0;
+    const hipError_t e = hipMalloc(&t->d_step_scratch, need);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(two-pass step scratch)");
+    t->step_scratch_bytes = need;
+  }
+  char* p = (char*)t->d_step_scratch;
+  ra->rec = (NewtonResume*)p;
+  ra->cls = (uint8_t*)(p + b_rec);
+  ra->list = (uint16_t*)(p + b_rec + b_cls);
+  ra->count = (unsigned*)(p + b_rec + b_cls + b_list);
+  ra->ntiles = ntiles;
+  return RC_OK;
 }
 
 rc_status make_params(rc_tables t, double dt, const rc_step_opts* o, StepParams* P, bool host) {
@@ -131,6 +280,8 @@ rc_status make_params(rc_tables t, double dt, const rc_step_opts* o, StepParams*
   if (o->block != 0 && (o->block < 64 || o->block > 256 || (o->block % 64) != 0))
     return set_error(RC_EINVAL, "block must be 0 or a multiple of 64 in [64, 256]");
   if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(RC_EINVAL, "dt must be finite and > 0");
+  if (o->passes < 0 || o->passes > 2) return set_error(RC_EINVAL, "passes must be 0, 1 or 2");
+  if (o->reserved != 0) return set_error(RC_EINVAL, "reserved option field must be 0");
   if (host) {
     fill_geom(t);
     P->g = &t->geom;
@@ -198,7 +349,31 @@ extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n,
         hipLaunchKernelGGL((k_step<SCHEME_RATES, Tab>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, n);
       return RC_OK;
   };
-  if (variant == RC_VARIANT_DIRECT) {
+  // two-pass Newton step (identical results; see k_newton_first)
+  const bool two_pass = opts->scheme == RC_SCHEME_NEWTON && opts->passes != 1 &&
+                        (variant == RC_VARIANT_CELL || variant == RC_VARIANT_GLOBAL);
+  const auto launch2 = [&](auto tab) -> rc_status {
+      using Tab = decltype(tab);
+      ResumeArgs ra;
+      rc_status rs = step_scratch(t, n, &ra);
+      if (rs != RC_OK) return rs;
+      hipLaunchKernelGGL((k_newton_first<Tab>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, ra, n);
+      hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)ra.ntiles), dim3(256), 0, hs, ra, n);
+      const int64_t g2 = (ra.ntiles + 7) / 8 * 8 * (kTile / 64);
+      hipLaunchKernelGGL((k_newton_resume<Tab>), dim3((unsigned)g2), dim3(64), 0, hs, tab, P, s, o, ra);
+      return RC_OK;
+  };
+  if (two_pass && variant == RC_VARIANT_CELL) {
+    st = ensure_cells(t, hs);
+    if (st != RC_OK) return st;
+    const rc_table_spec& sp = t->spec;
+    st = launch2(CellTab{(const float4*)t->d_cool, (const float*)t->d_coul, (const float4*)t->d_cool_cells,
+                         (const float*)t->d_coul_cells, sp.cool.n[1], sp.cool.n[2], sp.coul.n[1], sp.coul.n[2]});
+    if (st != RC_OK) return st;
+  } else if (two_pass) {
+    st = with_tab(t, launch2);
+    if (st != RC_OK) return st;
+  } else if (variant == RC_VARIANT_DIRECT) {
     hipLaunchKernelGGL(k_direct, dim3((unsigned)grid), dim3(block), 0, hs, P, s, o, n);
   } else if (variant == RC_VARIANT_CELL) {
     st = ensure_cells(t, hs);

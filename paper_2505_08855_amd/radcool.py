@@ -105,7 +105,8 @@ BLOCK_DTYPE = np.dtype([("first_cell", np.int64), ("n_cells", np.int32), ("state
 
 class StepOpts(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("variant", ctypes.c_int32), ("max_iter", ctypes.c_int32),
-                ("block", ctypes.c_int32), ("T_floor", ctypes.c_double), ("tol", ctypes.c_double)]
+                ("block", ctypes.c_int32), ("T_floor", ctypes.c_double), ("tol", ctypes.c_double),
+                ("passes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None

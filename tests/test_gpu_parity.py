@@ -319,3 +319,25 @@ def test_gas_floor_energy_tier(dev, imported64, spec64, block):
     assert 0.3 < off.mean() < 0.7 and np.all(out["Q_rad"][off] == 0.0)
     for k in ("T_e_new", "T_i_new"):
         assert np.max(rel_err(out[k], ref[k])) < ENERGY_TOL, k
+
+
+@pytest.mark.parametrize("n,dt_scale,floor", [(1, 1.0, 1e6), (4095, 1e3, 1e6), (4097, 1.0, 1e6),
+                                               (100_003, 1.0, 1e6), (100_003, 1e3, 3e7), (65_537, 1e2, 5e7)])
+def test_two_pass_equals_one_pass(dev, imported64, n, dt_scale, floor):
+    """The two-pass Newton step (first round in cell order, per-tile sort by
+    the first step, resumed rounds) runs the single pass's per-cell steps;
+    the two are separate kernels, so multiply-adds may be fused differently:
+    values agree to rounding, status exactly.  Sizes cover one cell, both
+    sides of a 4096-cell tile boundary and many tiles; the stiff steps and the
+    raised floors make first rounds end in floor probes."""
+    gt, _ = imported64
+    cells = W.workload(3, n=n)
+    st = to_dev(cells, dev)
+    dt = DT * dt_scale
+    one = to_np(R.cool_step(gt, st, dt, R.default_opts(T_floor=floor, passes=1), diagnostics=True))
+    two = to_np(R.cool_step(gt, st, dt, R.default_opts(T_floor=floor, passes=2), diagnostics=True))
+    assert np.array_equal(one["status"], two["status"])
+    for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc", "Q_brem", "Q_syn", "eta"):
+        assert np.max(rel_err(one[k], two[k])) < 1e-12, k
+    if floor > 1e6:
+        assert int(np.sum(one["status"] & R.ST_FLOOR)) > 0

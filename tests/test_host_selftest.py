@@ -331,3 +331,28 @@ def test_apply_cooling_on_host():
             assert Un[mu][7] == U0[mu][7]
     Un, _ = R.selftest_coupling_host(ne, te, ti, ten, tin, u, [U0[0], None, U0[2], None], dt)
     assert Un[1] is None and Un[3] is None
+
+
+@pytest.mark.parametrize("floor,dt_scale", [(1e6, 1.0), (3e6, 1e3), (5e7, 1e2)])
+def test_step_two_pass_identical_on_host(spec64, storage64, cells0_small, floor, dt_scale):
+    """The two-pass Newton step (first round, resume record, resumed solve)
+    gives bit-identical outputs to the single pass, including cells whose
+    first round ends in a floor probe (stiff cells around the floor)."""
+    resid, coeffs, _ = storage64
+    rng = np.random.default_rng(int(floor))
+    n = 400
+    n_e = 10 ** rng.uniform(14, 20, n)
+    T_e = floor * 10 ** rng.uniform(-0.6, 0.8, n)
+    T_i = T_e * 10 ** rng.uniform(-1.0, 1.5, n)
+    B = np.sqrt(8 * np.pi * n_e * 1.380649e-16 * (T_e + T_i) / 10 ** rng.uniform(-1, 2, n))
+    H = 10 ** rng.uniform(5, 9, n)
+    near = {"n_e": n_e, "T_e": T_e, "T_i": T_i, "B": B, "H": H}
+    cells = {f: np.concatenate([cells0_small[f], near[f]]) for f in W.FIELDS}
+    cells["T_e"][5] = np.nan                     # an invalid cell
+    dt = DT * dt_scale
+    one = R.selftest_step_host(R.default_spec(64), resid, coeffs, cells, dt, R.default_opts(T_floor=floor, passes=1))
+    two = R.selftest_step_host(R.default_spec(64), resid, coeffs, cells, dt, R.default_opts(T_floor=floor, passes=2))
+    for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc", "status"):
+        assert np.array_equal(one[k], two[k], equal_nan=(k != "status")), k
+    if dt_scale > 1.0:
+        assert (one["status"] & S.ST_FLOOR).sum() > 0
