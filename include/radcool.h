@@ -69,7 +69,12 @@ enum {
   RC_ST_CLAMP_COUL = 4,  /* a Coulomb-table coordinate of the input state was out of range (clamped) */
   RC_ST_FLOOR = 8,       /* the implicit update ended on the temperature floor */
   RC_ST_MAXITER = 16,    /* the solver hit max_iter; outputs are the best bracketed iterate */
-  RC_ST_GAS_FLOOR = 32   /* radiative cooling off for the step: input T_e + T_i below T_floor_gas */
+  RC_ST_GAS_FLOOR = 32,  /* radiative cooling off for the step: input T_e + T_i below T_floor_gas */
+  RC_ST_NO_RATE = 64     /* literal Compton reading only (RC_COMPTON_LITERAL): the cooling at the
+                            input state has no value, Q_rad = NaN.  Tables: a cooling-table corner
+                            of the cell's table cell holds no value (eta <= 0 at that node);
+                            DIRECT: eta <= 0 (or not finite) at the cell.  Not set when the
+                            cooling is off (T_e < T_floor, or the gas-temperature floor). */
 };
 
 /* One table's three axes, log10-spaced: node k of axis a is
@@ -84,6 +89,26 @@ typedef struct {
  * least-squares affine part in node-index space, which is kept in FP64). */
 enum { RC_VALUE_F32 = 0, RC_VALUE_BF16 = 1 };
 
+/* Readings of two printed formulas (Sec. II.C and II.G), selectable so that
+ * the printed forms stay on record and testable.
+ *   compton_exponent: RC_COMPTON_DERIVED (default) takes the Compton
+ *     enhancement with the exponent -1 - ln P / ln A, which makes it the
+ *     geometric series 1 + P (A-1) sum_{j<k} (PA)^j over k = ln(3 theta/E)/ln A
+ *     scatterings; RC_COMPTON_LITERAL takes the exponent 1 - ln P / ln A exactly
+ *     as printed, eta = 1 + P (A-1)/(1 - PA) [1 - (E/3 theta)^(1 - ln P/ln A)]
+ *     (eta = 1 for E >= 3 theta in both), which is negative wherever P A > 1.
+ *     Table nodes where that eta is not positive hold no value (NaN), so the
+ *     log2 table cannot be interpolated there: such cells get RC_ST_NO_RATE.
+ *     Tables built with RC_COMPTON_LITERAL serve the rates scheme only (rates
+ *     at the input state); the Newton and explicit schemes, the batched form
+ *     and the backward pass return RC_EUNSUPPORTED for them.
+ *   theta_i_mass: RC_THETA_I_MP (default) takes theta_i = k T_i / m_p c^2;
+ *     RC_THETA_I_ME takes the printed theta_i = k T_i / m_e c^2.  Only theta_i
+ *     changes (the prefactor keeps m_e / m_p).  Both readings give a complete
+ *     Coulomb table and every scheme accepts it. */
+enum { RC_COMPTON_DERIVED = 0, RC_COMPTON_LITERAL = 1 };
+enum { RC_THETA_I_MP = 0, RC_THETA_I_ME = 1 };
+
 typedef struct {
   rc_axes cool;          /* log10 N [cm^-2], log10 T_e [K], log10 B [G] */
   rc_axes coul;          /* log10 n_e [cm^-3], log10 T_e [K], log10 T_i [K] */
@@ -92,7 +117,9 @@ typedef struct {
                             rounded once more, to nearest-even bfloat16 (storage
                             experiment: half the table bytes, 2^-9 relative
                             rounding of the residual) */
-  int32_t reserved;      /* must be 0 */
+  int32_t compton_exponent;  /* RC_COMPTON_DERIVED (default) or RC_COMPTON_LITERAL */
+  int32_t theta_i_mass;      /* RC_THETA_I_MP (default) or RC_THETA_I_ME */
+  int32_t reserved;          /* must be 0 */
 } rc_table_spec;
 
 typedef struct rc_tables_s* rc_tables;   /* opaque, library-owned device tables */
@@ -118,8 +145,9 @@ typedef struct {
 typedef struct {
   double* T_e_new;
   double* T_i_new;
-  double* Q_rad;         /* bridged radiative cooling, erg cm^-3 s^-1 */
-  double* Q_cc;          /* Coulomb exchange, > 0 when ions heat electrons */
+  void* Q_rad;           /* bridged radiative cooling, erg cm^-3 s^-1; double, or float
+                            with opts.rate_dtype = RC_RATE_F32 */
+  void* Q_cc;            /* Coulomb exchange, > 0 when ions heat electrons; as Q_rad */
   uint8_t* status;       /* RC_ST_* bits */
   double* Q_brem;        /* optional diagnostics */
   double* Q_syn;
@@ -174,17 +202,30 @@ typedef struct {
                             first call and whenever n grows past what it holds), so
                             two-pass calls that overlap on one table handle must use
                             the same stream.  Ignored by other schemes and variants. */
+  int32_t grid;          /* batched form only: workgroups of the persistent launch,
+                            0 = library choice (4 per compute unit for
+                            rc_cool_step_batched; the tuned or the same default for a
+                            plan); otherwise 1 .. RC_MAX_GRID.  Ignored by the other
+                            entry points. */
+  int32_t rate_dtype;    /* element type of out->Q_rad and out->Q_cc: RC_RATE_F64
+                            (default, double) or RC_RATE_F32 (float, the FP64 value
+                            rounded to nearest: 8 instead of 16 bytes per cell) */
   int32_t reserved;      /* must be 0 */
 } rc_step_opts;
+
+enum { RC_RATE_F64 = 0, RC_RATE_F32 = 1 };
+
+#define RC_MAX_GRID 65536
 
 /* Fill *spec with the default axes (n points per axis):
  *   cooling: log10 N in [15, 29], log10 T_e in [5.95, 12.05], log10 B in [-0.5, 10.5]
  *   Coulomb: log10 n_e in [9.5, 20.5], log10 T_e in [5.95, 12.05], log10 T_i in [5.95, 14.05]
- * and ln_lambda = 20.  Returns RC_EINVAL for spec == NULL or n < 2. */
+ * and ln_lambda = 20, FP32 storage, the derived Compton exponent and theta_i with
+ * m_p.  Returns RC_EINVAL for spec == NULL or n < 2. */
 rc_status rc_default_spec(rc_table_spec* spec, int32_t n);
 
 /* Fill *opts with: Newton scheme, AUTO variant, max_iter 60, block 0,
- * T_floor 1e6 K, tol 1e-12, passes 0. */
+ * T_floor 1e6 K, tol 1e-12, passes 0, grid 0, FP64 rates. */
 rc_status rc_default_opts(rc_step_opts* opts);
 
 /* Build the four tables on the current device from the closed forms of Sec. II
@@ -245,9 +286,11 @@ typedef struct {
  * of n_states (1 .. RC_MAX_STATES) positive finite values.  Same per-cell
  * semantics as rc_cool_step; variants AUTO, GLOBAL and CELL (AUTO reads the
  * cell-blocked copy of FP32 tables, built on first use as described for
- * RC_VARIANT_CELL), others RC_EUNSUPPORTED.  Uses an internal 4-byte device
- * counter allocated on first use per table handle; calls that overlap on one
- * table handle must use the same stream.  Asynchronous on stream. */
+ * RC_VARIANT_CELL), others RC_EUNSUPPORTED.  opts->grid sets the number of
+ * workgroups (0 = 4 per compute unit).  Uses internal device scratch (the
+ * queue counter, the per-state dt and the per-workgroup item counts, 257 KiB)
+ * allocated on first use per table handle; calls that overlap on one table
+ * handle must use the same stream.  Asynchronous on stream. */
 rc_status rc_cool_step_batched(rc_tables t, const rc_state* state, int64_t n_total, const rc_block* blocks,
                                int32_t n_blocks, const double* dt_per_state, int32_t n_states,
                                const rc_step_opts* opts, const rc_out* out, void* stream);
@@ -256,8 +299,10 @@ rc_status rc_cool_step_batched(rc_tables t, const rc_state* state, int64_t n_tot
  * replay): the counter reset (a one-thread kernel) and the persistent kernel,
  * captured into a hipGraph and instantiated once.  With autotune != 0 the
  * workgroup size (64, 128, 256) and the persistent grid (1, 2, 4 or 8
- * workgroups per compute unit) are chosen by timing each candidate with HIP
- * events on the given stream (the outputs are written during tuning).
+ * workgroups per compute unit; only opts->grid when that is set) are chosen
+ * by timing each candidate with HIP events on the given stream (the outputs
+ * are written during tuning).  Without autotuning the plan takes opts->block
+ * (0 = 256) and opts->grid (0 = 4 per compute unit).
  * blocks is copied to the host once to validate every range (RC_EINVAL).
  * The plan keeps pointers, not copies, of state, out and blocks; the
  * cell-blocked table copy, when the variant reads it, is built before the
@@ -269,6 +314,17 @@ rc_status rc_plan_create(rc_tables t, const rc_state* state, int64_t n_total, co
                          rc_plan* plan);
 /* Replay the plan's graph on stream (asynchronous). */
 rc_status rc_plan_launch(rc_plan plan, void* stream);
+
+/* Work-queue diagnostics: how many work items (blocks) each workgroup of the
+ * most recent batched launch took from the queue, skipped blocks included (the
+ * counts sum to n_blocks).  rc_batched_workgroup_items reads the last
+ * rc_cool_step_batched launch on the table handle, rc_plan_workgroup_items the
+ * last launch of the plan (including its tuning launches).  Waits for the
+ * device (hipDeviceSynchronize), then copies min(grid, capacity) counts to the
+ * host array items (may be NULL); *grid (may be NULL) receives the number of
+ * workgroups of that launch.  RC_ESTATE when no launch has been made. */
+rc_status rc_batched_workgroup_items(rc_tables t, uint32_t* items, int32_t capacity, int32_t* grid);
+rc_status rc_plan_workgroup_items(rc_plan plan, uint32_t* items, int32_t capacity, int32_t* grid);
 /* Chosen launch shape and the tuned time of one launch (ms, 0 if not tuned). */
 rc_status rc_plan_info(rc_plan plan, int32_t* block, int32_t* grid, double* tuned_ms);
 rc_status rc_plan_destroy(rc_plan plan);
@@ -311,7 +367,8 @@ typedef struct {
  * 2x2 Jacobian per cell (implicit function theorem) at the converged solution
  * (on a floor-projected cell T_e' is constant).  The input-state rates Q_rad,
  * Q_cc add their direct derivatives.  RC_SCHEME_RATES is supported (T' = T);
- * RC_SCHEME_EXPLICIT16 gives RC_EUNSUPPORTED.  fwd must hold the outputs of a
+ * RC_SCHEME_EXPLICIT16, the DIRECT variant and tables of the literal Compton
+ * exponent give RC_EUNSUPPORTED.  fwd must hold the outputs of a
  * forward call with the same tables, state, dt and options.  With table
  * gradients the call keeps device scratch in the table handle: two records
  * per cell (about 160 bytes per cell) plus 24 doubles per table cell, allocated

@@ -241,8 +241,10 @@ def compton_eta_printed(n_e, T, H, nu_c):
     P = -np.expm1(-tau_scattering(n_e, H))
     A = 1.0 + 4.0 * th + 16.0 * th ** 2
     E = K.H_PLANCK * np.asarray(nu_c, dtype=np.float64) / K.ME_C2
-    expo = 1.0 - np.log(P) / np.log(A)
-    return 1.0 + P * (A - 1.0) / (1.0 - P * A) * (1.0 - (E / (3.0 * th)) ** expo)
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        expo = 1.0 - np.log(P) / np.log(A)
+        eta = 1.0 + P * (A - 1.0) / (1.0 - P * A) * (1.0 - (E / (3.0 * th)) ** expo)
+    return np.where(E < 3.0 * th, eta, 1.0)
 
 
 # ---------------------------------------------------------------------------
@@ -281,7 +283,8 @@ def hubeny_total_rewritten(q_thin_v, T, H, tau_sca):
 
 
 def coulomb_ratio(T_e, T_i, ion_mass=K.M_P):
-    """R(theta_e, theta_i) of eq. coulomb_collisions with the e^-z factors cancelled.
+    """R(theta_e, theta_i) of eq. coulomb_collisions with the e^-z factors cancelled,
+    theta_i = k T_i / (ion_mass c^2).
 
     K2(1/th_i) K2(1/th_e) = kve2(1/th_i) kve2(1/th_e) e^{-1/th_m} and
     K_n(1/th_m) = kve_n(1/th_m) e^{-1/th_m} because 1/th_m = 1/th_e + 1/th_i,
@@ -296,33 +299,45 @@ def coulomb_ratio(T_e, T_i, ion_mass=K.M_P):
     return num / den
 
 
-def coulomb_coeff(n_e, T_e, T_i, ln_lambda=K.LN_LAMBDA, ion_mass=K.M_P):
-    """Q_cc / (T_i - T_e) > 0, eq. coulomb_collisions with rho/m_p = n_e, m_i = m_p."""
+def coulomb_coeff(n_e, T_e, T_i, ln_lambda=K.LN_LAMBDA, ion_mass=K.M_P, theta_i_mass=None):
+    """Q_cc / (T_i - T_e) > 0, eq. coulomb_collisions with rho/m_p = n_e, m_i = m_p.
+
+    theta_i_mass is the mass in theta_i = k T_i / m c^2 (default: the ion
+    mass; K.M_E gives the printed form).  The prefactor keeps m_e / m_i."""
     n_e = np.asarray(n_e, dtype=np.float64)
     pref = 1.5 * (K.M_E / ion_mass) * n_e * n_e * ln_lambda * K.C_LIGHT * K.K_B * K.SIGMA_T
-    return pref * coulomb_ratio(T_e, T_i, ion_mass)
+    return pref * coulomb_ratio(T_e, T_i, ion_mass if theta_i_mass is None else theta_i_mass)
 
 
-def q_coulomb(n_e, T_e, T_i, ln_lambda=K.LN_LAMBDA, ion_mass=K.M_P):
+def q_coulomb(n_e, T_e, T_i, ln_lambda=K.LN_LAMBDA, ion_mass=K.M_P, theta_i_mass=None):
     """Q_cc, positive when ions heat electrons."""
-    return (np.asarray(T_i, dtype=np.float64) - T_e) * coulomb_coeff(n_e, T_e, T_i, ln_lambda, ion_mass)
+    return (np.asarray(T_i, dtype=np.float64) - T_e) * coulomb_coeff(n_e, T_e, T_i, ln_lambda, ion_mass,
+                                                                      theta_i_mass)
 
 
 # ---------------------------------------------------------------------------
 # direct (table-free) rates at one state
 
 
-def direct_rates(n_e, T_e, T_i, B, H):
+def direct_rates(n_e, T_e, T_i, B, H, compton="derived", theta_i_mass=K.M_P):
     """All rates at the state from the closed forms, no tables.
 
     Returns dict with q_brem, q_syn, eta, q_thin, q_rad (bridged) and q_cc.
+    compton="literal" takes the printed exponent (compton_eta_printed);
+    q_rad is NaN where that eta is not positive (no cooling value there).
+    theta_i_mass is the mass in theta_i (K.M_E: the printed form).
     """
     n_e, T_e, T_i, B, H = (np.asarray(v, dtype=np.float64) for v in (n_e, T_e, T_i, B, H))
     qb = q_brem(n_e, T_e)
     syn = synchrotron(n_e, T_e, B, H)
-    eta = compton_eta(n_e, T_e, H, syn["nu_c"])
+    if compton == "literal":
+        eta = compton_eta_printed(n_e, T_e, H, syn["nu_c"])
+    else:
+        eta = compton_eta(n_e, T_e, H, syn["nu_c"])
     qt = q_thin(qb, eta, syn["q_syn"])
     ts = tau_scattering(n_e, H)
+    with np.errstate(invalid="ignore"):
+        q_rad = hubeny_total_rewritten(qt, T_e, H, ts)
+    q_rad = np.where((eta > 0.0) & np.isfinite(eta), q_rad, np.nan)
     return {"q_brem": qb, "q_syn": syn["q_syn"], "eta": eta, "q_thin": qt,
-            "q_rad": hubeny_total_rewritten(qt, T_e, H, ts),
-            "q_cc": q_coulomb(n_e, T_e, T_i)}
+            "q_rad": q_rad, "q_cc": q_coulomb(n_e, T_e, T_i, theta_i_mass=theta_i_mass)}

@@ -43,6 +43,7 @@ ST_CLAMP_COUL = 4
 ST_FLOOR = 8
 ST_MAXITER = 16
 ST_MULTIROOT = 32
+ST_NO_RATE = 64       # literal Compton reading: a cooling-table corner of the cell has no value
 
 
 class TableSet:
@@ -94,7 +95,8 @@ def table_rates(ts, n_e, T_e, T_i, B, H, T_floor=1.0e6):
     q_thin = q_brem + v_eta * q_syn
     q_rad = np.where(T_e < T_floor, 0.0, bridge(q_thin, T_e, H, n_e))
     v_c, cl_coul = ts.coulomb(n_e, T_e, T_i)
-    status = np.where(cl_cool, ST_CLAMP_COOL, 0) | np.where(cl_coul, ST_CLAMP_COUL, 0)
+    status = (np.where(cl_cool, ST_CLAMP_COOL, 0) | np.where(cl_coul, ST_CLAMP_COUL, 0) |
+              np.where(np.isnan(q_rad) & ~invalid_mask(n_e, T_e, T_i, B, H), ST_NO_RATE, 0))
     return {"q_brem": q_brem, "q_syn": q_syn, "eta": v_eta, "q_thin": q_thin,
             "q_rad": q_rad, "q_cc": (T_i - T_e) * v_c, "status": status.astype(np.uint8)}
 

@@ -60,13 +60,18 @@ def _default_coul(n):
 @dataclass(frozen=True)
 class TableSpec:
     """Axes of the cooling tables (log10 N, log10 T_e, log10 B) and of the
-    Coulomb table (log10 n_e, log10 T_e, log10 T_i)."""
+    Coulomb table (log10 n_e, log10 T_e, log10 T_i), and the readings of two
+    printed formulas: ``compton`` "derived" (exponent -1 - ln P / ln A, the
+    default) or "literal" (1 - ln P / ln A as printed, II.C); ``theta_i_mass``
+    "m_p" (default) or "m_e" (theta_i = k T_i / m_e c^2 as printed, II.G)."""
     cool: tuple = field(default_factory=lambda: _default_cool(64))
     coul: tuple = field(default_factory=lambda: _default_coul(64))
+    compton: str = "derived"
+    theta_i_mass: str = "m_p"
 
     @staticmethod
-    def default(n=64):
-        return TableSpec(_default_cool(n), _default_coul(n))
+    def default(n=64, compton="derived", theta_i_mass="m_p"):
+        return TableSpec(_default_cool(n), _default_coul(n), compton, theta_i_mass)
 
     def axes(self, name):
         return self.coul if name == "coul" else self.cool
@@ -92,14 +97,22 @@ def build_cooling(spec, chunk=1 << 18):
         brem[sl] = np.log2(physics.q_brem(N[sl], T[sl]))        # H = 1: n_e = N
         sy = physics.synchrotron(N[sl], T[sl], B[sl], one[sl])
         syn[sl] = np.log2(sy["q_syn"])
-        eta[sl] = np.log2(physics.compton_eta(N[sl], T[sl], one[sl], sy["nu_c"]))
+        if spec.compton == "literal":
+            # the printed exponent: eta <= 0 wherever P A > 1, and such a node
+            # has no log2 value (NaN)
+            e = physics.compton_eta_printed(N[sl], T[sl], one[sl], sy["nu_c"])
+            ok = (e > 0.0) & np.isfinite(e)
+            eta[sl] = np.where(ok, np.log2(np.where(ok, e, 1.0)), np.nan)
+        else:
+            eta[sl] = np.log2(physics.compton_eta(N[sl], T[sl], one[sl], sy["nu_c"]))
     shape = uN.shape
     return {"brem": brem.reshape(shape), "synch": syn.reshape(shape), "eta": eta.reshape(shape)}
 
 
 def build_coulomb(spec):
     un, ue, ui = _grid(spec.coul)
-    return np.log2(physics.coulomb_coeff(10.0 ** un, 10.0 ** ue, 10.0 ** ui))
+    m_ti = physics.K.M_E if spec.theta_i_mass == "m_e" else physics.K.M_P
+    return np.log2(physics.coulomb_coeff(10.0 ** un, 10.0 ** ue, 10.0 ** ui, theta_i_mass=m_ti))
 
 
 def build_tables(spec=None):

@@ -314,6 +314,8 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
     return set_error(RC_EUNSUPPORTED, "rc_cool_step_backward: the explicit scheme has no adjoint");
   if (opts->variant == RC_VARIANT_DIRECT)
     return set_error(RC_EUNSUPPORTED, "rc_cool_step_backward: the DIRECT variant has no table adjoint");
+  if (t->spec.compton_exponent == RC_COMPTON_LITERAL)
+    return set_error(RC_EUNSUPPORTED, "rc_cool_step_backward: tables of the literal Compton exponent have no adjoint");
   const bool newton = opts->scheme == RC_SCHEME_NEWTON;
   if (n > 0 && (!state->n_e || !state->T_e || !state->T_i || !state->B || !state->H))
     return set_error(RC_EINVAL, "rc_cool_step_backward: a state pointer is NULL");

@@ -22,11 +22,14 @@ struct BatchArgs {
   int64_t n_total;
   unsigned* counter;      // work-queue counter
   const double* dt;       // per-state dt, device memory
+  unsigned* wg_items;     // per workgroup: work items taken from the queue
 };
 
 // device scratch of a batched launch: the counter in the first 256 bytes, the
-// per-state dt after it
-constexpr size_t kBatchScratch = 256 + sizeof(double) * RC_MAX_STATES;
+// per-state dt after it, then one item count per workgroup
+constexpr size_t kBatchDtOffset = 256;
+constexpr size_t kBatchItemsOffset = kBatchDtOffset + sizeof(double) * RC_MAX_STATES;
+constexpr size_t kBatchScratch = kBatchItemsOffset + sizeof(unsigned) * RC_MAX_GRID;
 
 __global__ void k_reset_counter(unsigned* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0u;
@@ -34,17 +37,20 @@ __global__ void k_reset_counter(unsigned* counter) {
 
 // Each workgroup repeatedly takes the next block index from the queue and
 // advances all of that block's cells; it exits when the index passes the last
-// block, which every workgroup reaches because the counter only grows.
+// block, which every workgroup reaches because the counter only grows.  On
+// exit it records how many items it took.
 template <int SCHEME, class Tab>
 __global__ __launch_bounds__(256) void k_batched(Tab tab, StepParams P, StateArgs s, OutArgs o, BatchArgs b) {
   __shared__ int item;
   const bool diag = o.Q_brem || o.Q_syn || o.eta;
+  unsigned taken = 0;
   for (;;) {
     if (threadIdx.x == 0) item = (int)atomicAdd(b.counter, 1u);
     __syncthreads();
     const int w = item;
     __syncthreads();
     if (w >= b.n_blocks) break;
+    ++taken;
     const rc_block blk = b.blocks[w];
     if (blk.first_cell < 0 || blk.n_cells <= 0 || blk.first_cell > b.n_total - blk.n_cells || blk.state_id < 0 ||
         blk.state_id >= b.n_states)
@@ -57,6 +63,7 @@ __global__ __launch_bounds__(256) void k_batched(Tab tab, StepParams P, StateArg
       store(o, i, r);
     }
   }
+  if (threadIdx.x == 0) b.wg_items[blockIdx.x] = taken;
 }
 
 namespace {
@@ -91,8 +98,9 @@ rc_status check_batch_args(rc_tables t, const rc_state* state, int64_t n_total, 
 // counter + per-state dt in device scratch; dt copied in on the stream
 rc_status fill_scratch(void* scratch, const double* dts, int n_states, hipStream_t hs, BatchArgs* b) {
   b->counter = (unsigned*)scratch;
-  b->dt = (const double*)((char*)scratch + 256);
-  const hipError_t e = hipMemcpyAsync((char*)scratch + 256, dts, sizeof(double) * n_states,
+  b->dt = (const double*)((char*)scratch + kBatchDtOffset);
+  b->wg_items = (unsigned*)((char*)scratch + kBatchItemsOffset);
+  const hipError_t e = hipMemcpyAsync((char*)scratch + kBatchDtOffset, dts, sizeof(double) * n_states,
                                       hipMemcpyHostToDevice, hs);
   return e == hipSuccess ? RC_OK : hip_fail(e, "batched: copying dt_per_state");
 }
@@ -149,6 +157,7 @@ struct rc_plan_s {
   bool cells = false;   // the step reads the cell-blocked table copy
   int block = 256, grid = 0;
   double tuned_ms = 0.0;
+  int last_grid = 0;    // workgroups of the plan's most recent launch (0 = none yet)
   unsigned* counter = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -173,11 +182,35 @@ extern "C" rc_status rc_cool_step_batched(rc_tables t, const rc_state* state, in
   st = fill_scratch(t->d_counter, dt_per_state, n_states, (hipStream_t)stream, &b);
   if (st != RC_OK) return st;
   StateArgs s{state->n_e, state->T_e, state->T_i, state->B, state->H, state->T_floor_gas};
-  OutArgs o{out->T_e_new, out->T_i_new, out->Q_rad, out->Q_cc, out->Q_brem, out->Q_syn, out->eta, out->status};
+  const OutArgs o = out_args(out, opts);
   const int block = opts->block ? opts->block : 256;
-  const int grid = compute_units() * 4;
+  const int grid = opts->grid ? opts->grid : compute_units() * 4;
   const hipError_t e = launch_batched(opts->scheme, t, cells, P, s, o, b, block, grid, (hipStream_t)stream);
-  return e == hipSuccess ? RC_OK : hip_fail(e, "rc_cool_step_batched launch");
+  if (e != hipSuccess) return hip_fail(e, "rc_cool_step_batched launch");
+  t->batched_grid = grid;
+  return RC_OK;
+}
+
+namespace {
+rc_status copy_items(const void* scratch, int grid, uint32_t* items, int32_t capacity, int32_t* grid_out,
+                     const char* who) {
+  if (grid <= 0 || !scratch) return set_error(RC_ESTATE, who);
+  if (capacity < 0) return set_error(RC_EINVAL, "workgroup items: negative capacity");
+  hipError_t e = hipDeviceSynchronize();
+  const int m = grid < capacity ? grid : capacity;
+  if (e == hipSuccess && items && m > 0)
+    e = hipMemcpy(items, (const char*)scratch + kBatchItemsOffset, sizeof(unsigned) * (size_t)m,
+                  hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "workgroup items: reading the counts");
+  if (grid_out) *grid_out = grid;
+  return RC_OK;
+}
+}  // namespace
+
+extern "C" rc_status rc_batched_workgroup_items(rc_tables t, uint32_t* items, int32_t capacity, int32_t* grid) {
+  if (!handle_ok(t)) return set_error(RC_ESTATE, "rc_batched_workgroup_items: invalid table handle");
+  return copy_items(t->d_counter, t->batched_grid, items, capacity, grid,
+                    "rc_batched_workgroup_items: no batched launch on this table handle yet");
 }
 
 extern "C" rc_status rc_plan_create(rc_tables t, const rc_state* state, int64_t n_total, const rc_block* blocks,
@@ -205,7 +238,7 @@ extern "C" rc_status rc_plan_create(rc_tables t, const rc_state* state, int64_t 
   p->t = t;
   p->P = P;
   p->s = StateArgs{state->n_e, state->T_e, state->T_i, state->B, state->H, state->T_floor_gas};
-  p->o = OutArgs{out->T_e_new, out->T_i_new, out->Q_rad, out->Q_cc, out->Q_brem, out->Q_syn, out->eta, out->status};
+  p->o = out_args(out, opts);
   p->b = b;
   p->scheme = opts->scheme;
   p->cells = batched_cells(t, opts);
@@ -220,7 +253,7 @@ extern "C" rc_status rc_plan_create(rc_tables t, const rc_state* state, int64_t 
   if (st != RC_OK) { (void)hipFree(p->counter); delete p; return st; }
   const int cus = compute_units();
   p->block = opts->block ? opts->block : 256;
-  p->grid = cus * 4;
+  p->grid = opts->grid ? opts->grid : cus * 4;
   if (autotune) {
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
@@ -229,8 +262,9 @@ extern "C" rc_status rc_plan_create(rc_tables t, const rc_state* state, int64_t 
     const int per_cu[4] = {1, 2, 4, 8};
     float best = 1e30f;
     for (int bi = 0; bi < 3; ++bi) {
-      for (int gi = 0; gi < 4; ++gi) {
-        const int blk = blocks_c[bi], grid = cus * per_cu[gi];
+      for (int gi = 0; gi < (opts->grid ? 1 : 4); ++gi) {
+        const int blk = blocks_c[bi], grid = opts->grid ? opts->grid : cus * per_cu[gi];
+        p->last_grid = grid;
         e = launch_batched(p->scheme, t, p->cells, p->P, p->s, p->o, p->b, blk, grid, hs);   // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, hs);
         if (e == hipSuccess) e = launch_batched(p->scheme, t, p->cells, p->P, p->s, p->o, p->b, blk, grid, hs);
@@ -279,7 +313,15 @@ extern "C" rc_status rc_plan_launch(rc_plan plan, void* stream) {
   if (!plan || plan->magic != kPlanMagic) return set_error(RC_ESTATE, "rc_plan_launch: invalid plan");
   if (!handle_ok(plan->t)) return set_error(RC_ESTATE, "rc_plan_launch: the plan's tables were destroyed");
   const hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
-  return e == hipSuccess ? RC_OK : hip_fail(e, "rc_plan_launch");
+  if (e != hipSuccess) return hip_fail(e, "rc_plan_launch");
+  plan->last_grid = plan->grid;
+  return RC_OK;
+}
+
+extern "C" rc_status rc_plan_workgroup_items(rc_plan plan, uint32_t* items, int32_t capacity, int32_t* grid) {
+  if (!plan || plan->magic != kPlanMagic) return set_error(RC_ESTATE, "rc_plan_workgroup_items: invalid plan");
+  return copy_items(plan->counter, plan->last_grid, items, capacity, grid,
+                    "rc_plan_workgroup_items: the plan has not been launched yet");
 }
 
 extern "C" rc_status rc_plan_info(rc_plan plan, int32_t* block, int32_t* grid, double* tuned_ms) {

@@ -43,7 +43,9 @@ bool axes_ok(const rc_axes& a) {
 
 bool spec_ok(const rc_table_spec* s) {
   return s && axes_ok(s->cool) && axes_ok(s->coul) && std::isfinite(s->ln_lambda) && s->ln_lambda > 0.0 &&
-         (s->value_dtype == RC_VALUE_F32 || s->value_dtype == RC_VALUE_BF16) && s->reserved == 0;
+         (s->value_dtype == RC_VALUE_F32 || s->value_dtype == RC_VALUE_BF16) &&
+         (s->compton_exponent == RC_COMPTON_DERIVED || s->compton_exponent == RC_COMPTON_LITERAL) &&
+         (s->theta_i_mass == RC_THETA_I_MP || s->theta_i_mass == RC_THETA_I_ME) && s->reserved == 0;
 }
 
 int64_t volume(const rc_axes& a) { return (int64_t)a.n[0] * a.n[1] * a.n[2]; }
@@ -79,6 +81,8 @@ extern "C" rc_status rc_default_spec(rc_table_spec* spec, int32_t n) {
   }
   spec->ln_lambda = 20.0;
   spec->value_dtype = RC_VALUE_F32;
+  spec->compton_exponent = RC_COMPTON_DERIVED;
+  spec->theta_i_mass = RC_THETA_I_MP;
   spec->reserved = 0;
   return RC_OK;
 }
@@ -92,6 +96,8 @@ extern "C" rc_status rc_default_opts(rc_step_opts* o) {
   o->T_floor = 1.0e6;
   o->tol = 1.0e-12;
   o->passes = 0;
+  o->grid = 0;
+  o->rate_dtype = RC_RATE_F64;
   o->reserved = 0;
   return RC_OK;
 }
@@ -308,7 +314,7 @@ bool handle_ok(rc_tables t) { return t && t->magic == kTablesMagic; }
 }  // namespace rc
 
 // node evaluation: one thread per node
-__global__ void k_nodes_cool(rc_axes ax, double* yb, double* ys, double* ye) {
+__global__ void k_nodes_cool(rc_axes ax, int compton_literal, double* yb, double* ys, double* ye) {
   const int64_t n = (int64_t)ax.n[0] * ax.n[1] * ax.n[2];
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -319,11 +325,11 @@ __global__ void k_nodes_cool(rc_axes ax, double* yb, double* ys, double* ye) {
     const double T = exp10(ax.lo[1] + i1 * (ax.hi[1] - ax.lo[1]) / (ax.n[1] - 1));
     const double B = exp10(ax.lo[2] + i2 * (ax.hi[2] - ax.lo[2]) / (ax.n[2] - 1));
     yb[idx] = node_brem(N, T);
-    node_synch_eta(N, T, B, &ys[idx], &ye[idx]);
+    node_synch_eta(N, T, B, compton_literal != 0, &ys[idx], &ye[idx]);
   }
 }
 
-__global__ void k_nodes_coul(rc_axes ax, double ln_lambda, double* yc) {
+__global__ void k_nodes_coul(rc_axes ax, double ln_lambda, int theta_i_me, double* yc) {
   const int64_t n = (int64_t)ax.n[0] * ax.n[1] * ax.n[2];
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -333,7 +339,7 @@ __global__ void k_nodes_coul(rc_axes ax, double ln_lambda, double* yc) {
     const double ne = exp10(ax.lo[0] + i0 * (ax.hi[0] - ax.lo[0]) / (ax.n[0] - 1));
     const double Te = exp10(ax.lo[1] + i1 * (ax.hi[1] - ax.lo[1]) / (ax.n[1] - 1));
     const double Ti = exp10(ax.lo[2] + i2 * (ax.hi[2] - ax.lo[2]) / (ax.n[2] - 1));
-    yc[idx] = node_coul(ne, Te, Ti, ln_lambda);
+    yc[idx] = node_coul(ne, Te, Ti, ln_lambda, theta_i_me != 0);
   }
 }
 
@@ -345,9 +351,18 @@ rc_status finish_from_values(rc_tables_s* t, const std::vector<double>& y, void*
     const rc_axes& a = (k < 3) ? t->spec.cool : t->spec.coul;
     const double* src = y.data() + (k < 3 ? k * vc : 3 * vc);
     const int64_t v = (k < 3) ? vc : vk;
-    for (int64_t i = 0; i < v; ++i)
-      if (!std::isfinite(src[i])) return fail(RC_EDEVICE, "table build produced a non-finite node value");
-    affine_fit(src, a.n, t->coef[k]);
+    bool holes = false;
+    for (int64_t i = 0; i < v; ++i) {
+      if (std::isfinite(src[i])) continue;
+      // the literal Compton reading leaves eta nodes without a value (NaN)
+      if (!(k == RC_TAB_ETA && t->spec.compton_exponent == RC_COMPTON_LITERAL && std::isnan(src[i])))
+        return fail(RC_EDEVICE, "table build produced a non-finite node value");
+      holes = true;
+    }
+    // a table with nodes without a value keeps a zero affine part: the
+    // residual is the log2 value itself (NaN stays NaN)
+    if (holes) for (int j = 0; j < 4; ++j) t->coef[k][j] = 0.0;
+    else affine_fit(src, a.n, t->coef[k]);
     float* dst = t->resid.data() + (k < 3 ? k * vc : 3 * vc);
     int64_t idx = 0;
     for (int i0 = 0; i0 < a.n[0]; ++i0)
@@ -378,8 +393,10 @@ extern "C" rc_status rc_build_tables(const rc_table_spec* spec, void* stream, rc
   const int blk = 128;
   const int gc = (int)std::min<int64_t>((vc + blk - 1) / blk, 65535);
   const int gk = (int)std::min<int64_t>((vk + blk - 1) / blk, 65535);
-  hipLaunchKernelGGL(k_nodes_cool, dim3(gc), dim3(blk), 0, s, spec->cool, d_y, d_y + vc, d_y + 2 * vc);
-  hipLaunchKernelGGL(k_nodes_coul, dim3(gk), dim3(blk), 0, s, spec->coul, spec->ln_lambda, d_y + 3 * vc);
+  hipLaunchKernelGGL(k_nodes_cool, dim3(gc), dim3(blk), 0, s, spec->cool,
+                     spec->compton_exponent == RC_COMPTON_LITERAL ? 1 : 0, d_y, d_y + vc, d_y + 2 * vc);
+  hipLaunchKernelGGL(k_nodes_coul, dim3(gk), dim3(blk), 0, s, spec->coul, spec->ln_lambda,
+                     spec->theta_i_mass == RC_THETA_I_ME ? 1 : 0, d_y + 3 * vc);
   e = hipGetLastError();
   std::vector<double> y;
   if (e == hipSuccess) {
@@ -410,8 +427,15 @@ extern "C" rc_status rc_tables_import(const rc_table_spec* spec, const float* re
   rc_tables_s* t = nullptr;
   rc_status st = new_tables(spec, &t);
   if (st != RC_OK) return st;
+  const int64_t vc_i = volume(spec->cool);
   for (size_t i = 0; i < t->resid.size(); ++i) {
-    if (!std::isfinite(resid[i])) { destroy_tables(t); return fail(RC_EINVAL, "rc_tables_import: non-finite residual"); }
+    // nodes without a value (NaN) only in the eta table of the literal Compton reading
+    const bool hole_ok = spec->compton_exponent == RC_COMPTON_LITERAL && (int64_t)i >= 2 * vc_i &&
+                         (int64_t)i < 3 * vc_i && std::isnan(resid[i]);
+    if (!std::isfinite(resid[i]) && !hole_ok) {
+      destroy_tables(t);
+      return fail(RC_EINVAL, "rc_tables_import: non-finite residual");
+    }
     t->resid[i] = resid[i];
   }
   for (int k = 0; k < 4; ++k)
@@ -453,7 +477,7 @@ extern "C" rc_status rc_tables_destroy(rc_tables t) {
 
 namespace {
 
-constexpr char kFileMagic[8] = {'R', 'C', 'T', 'A', 'B', 'L', 'E', '2'};
+constexpr char kFileMagic[8] = {'R', 'C', 'T', 'A', 'B', 'L', 'E', '3'};
 
 // FNV-1a, 64 bit, over the payload bytes
 uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
@@ -531,10 +555,10 @@ extern "C" rc_status rc_selftest_node_host(const rc_table_spec* spec, int32_t ta
   if (table == RC_TAB_BREM) {
     *value = node_brem(u0, u1);
   } else if (table == RC_TAB_COUL) {
-    *value = node_coul(u0, u1, u2, spec->ln_lambda);
+    *value = node_coul(u0, u1, u2, spec->ln_lambda, spec->theta_i_mass == RC_THETA_I_ME);
   } else {
     double ys, ye;
-    node_synch_eta(u0, u1, u2, &ys, &ye);
+    node_synch_eta(u0, u1, u2, spec->compton_exponent == RC_COMPTON_LITERAL, &ys, &ye);
     *value = (table == RC_TAB_SYNCH) ? ys : ye;
   }
   return RC_OK;

@@ -29,6 +29,7 @@ struct rc_tables_s {
   rc::TableGeom geom{};             // axes and affine coefficients (host copy)
   rc::TableGeom* d_geom = nullptr;  // the same in device memory, read by the kernels
   void* d_counter = nullptr;        // work-queue counter of the batched kernel (allocated on first use)
+  int batched_grid = 0;             // workgroups of the last rc_cool_step_batched launch (0 = none)
   void* d_gscratch = nullptr;       // backward: table-gradient records and accumulators (first use)
   size_t gscratch_bytes = 0;        // its size (grows with the cell count)
   void* d_step_scratch = nullptr;   // two-pass Newton step: resume records, classes, tile lists (first use)

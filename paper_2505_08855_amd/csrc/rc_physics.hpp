@@ -233,13 +233,28 @@ RC_HD double ln_eta(double n_e, double T, double H, double nu_c) {
   return log1p(P * (A - 1.0) * ratio);
 }
 
+// eta_comp at nu_c with the exponent exactly as printed, 1 - ln P / ln A:
+// 1 + P (A-1)/(1 - PA) [1 - (E/3 theta)^(1 - ln P/ln A)], 1 for E >= 3 theta.
+// Negative wherever P A > 1 (the reading not taken by default).
+RC_HD double eta_literal(double n_e, double T, double H, double nu_c) {
+  const double th = theta_e(T);
+  const double E = kH * nu_c / kMeC2;
+  if (!(E < 3.0 * th)) return 1.0;
+  const double tau = 2.0 * n_e * kSigmaT * H;
+  const double P = -expm1(-tau);
+  const double A = 1.0 + 4.0 * th + 16.0 * th * th;
+  const double expo = 1.0 - log(P) / log(A);
+  return 1.0 + P * (A - 1.0) / (1.0 - P * A) * (1.0 - pow(E / (3.0 * th), expo));
+}
+
 // ---------------------------------------------------------------- Sec. II.G
-// Q_cc / (T_i - T_e) with rho/m_p = n_i = n_e, m_i = m_p, theta_i = k T_i / m_p c^2.
+// Q_cc / (T_i - T_e) with rho/m_p = n_i = n_e, m_i = m_p, theta_i = k T_i / m_p c^2
+// (theta_i = k T_i / m_e c^2, as printed, when theta_i_me).
 // The e^-z factors of K2(1/th_i) K2(1/th_e) and K_n(1/th_m) cancel exactly
 // (1/th_m = 1/th_e + 1/th_i), so only scaled Bessel functions appear.
-RC_HD double ln_coulomb_coeff(double n_e, double T_e, double T_i, double ln_lambda) {
+RC_HD double ln_coulomb_coeff(double n_e, double T_e, double T_i, double ln_lambda, bool theta_i_me = false) {
   const double te = theta_e(T_e);
-  const double ti = theta_p(T_i);
+  const double ti = theta_i_me ? theta_e(T_i) : theta_p(T_i);
   const double s = te + ti;
   const double zm = 1.0 / te + 1.0 / ti;
   double m0, m1, m2, e0, e1, e2, i0, i1, i2;
@@ -256,14 +271,21 @@ RC_HD double ln_coulomb_coeff(double n_e, double T_e, double T_i, double ln_lamb
 // tables; see the reduction note in radcool.h).
 RC_HD double node_brem(double N, double T) { return (2.0 * log(N) + log(brem_coeff(T))) / kLn2; }
 
-RC_HD void node_synch_eta(double N, double T, double B, double* y_s, double* y_eta) {
+// With the literal Compton exponent a node whose eta is not positive has no
+// log2 value: NaN.
+RC_HD void node_synch_eta(double N, double T, double B, bool compton_literal, double* y_s, double* y_eta) {
   const SynchResult sr = synchrotron(N, T, B, 1.0);
   *y_s = sr.ln_q / kLn2;
-  *y_eta = ln_eta(N, T, 1.0, sr.nu_c) / kLn2;
+  if (compton_literal) {
+    const double eta = eta_literal(N, T, 1.0, sr.nu_c);
+    *y_eta = (eta > 0.0 && isfinite(eta)) ? log(eta) / kLn2 : __builtin_nan("");
+  } else {
+    *y_eta = ln_eta(N, T, 1.0, sr.nu_c) / kLn2;
+  }
 }
 
-RC_HD double node_coul(double n_e, double T_e, double T_i, double ln_lambda) {
-  return ln_coulomb_coeff(n_e, T_e, T_i, ln_lambda) / kLn2;
+RC_HD double node_coul(double n_e, double T_e, double T_i, double ln_lambda, bool theta_i_me) {
+  return ln_coulomb_coeff(n_e, T_e, T_i, ln_lambda, theta_i_me) / kLn2;
 }
 
 }  // namespace rc

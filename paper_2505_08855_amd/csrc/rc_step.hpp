@@ -47,7 +47,8 @@
 namespace rc {
 
 enum : unsigned char {
-  ST_INVALID = 1, ST_CLAMP_COOL = 2, ST_CLAMP_COUL = 4, ST_FLOOR = 8, ST_MAXITER = 16, ST_GAS_FLOOR = 32
+  ST_INVALID = 1, ST_CLAMP_COOL = 2, ST_CLAMP_COUL = 4, ST_FLOOR = 8, ST_MAXITER = 16, ST_GAS_FLOOR = 32,
+  ST_NO_RATE = 64
 };
 
 // Electron floor of a cell whose cooling is switched off for the step (its
@@ -78,6 +79,7 @@ struct StepParams {
   double dt, T_floor, tol, ln_lambda;
   double ln_T_floor, sqrt_tol;   // log(T_floor), sqrt(tol)
   int max_iter, scheme;
+  int compton_literal, theta_i_me;   // readings of the table set (used by the closed forms)
 };
 
 struct Coord {
@@ -731,6 +733,8 @@ struct CellSolver {
     gather(cT, ce, ci, on);
     q_rad(T_e, cT, on, &q, &dq);
     o->q_rad = q;
+    // a cooling-table corner without a value (literal Compton reading)
+    if (!(q == q)) o->status |= ST_NO_RATE;
     o->q_cc = (T_i - T_e) * kcoul_at(ce, ci, &dlx, &dlz);
     o->T_e_new = T_e;
     o->T_i_new = T_i;
@@ -815,17 +819,19 @@ RC_HD void direct_rates(const StepParams& P, double n_e, double T_e, double T_i,
   o->q_brem = n_e * n_e * brem_coeff(T_e);
   const SynchResult sr = synchrotron(n_e, T_e, B, H);
   o->q_syn = exp(sr.ln_q);
-  o->eta = exp(ln_eta(n_e, T_e, H, sr.nu_c));
+  o->eta = P.compton_literal ? eta_literal(n_e, T_e, H, sr.nu_c) : exp(ln_eta(n_e, T_e, H, sr.nu_c));
   const double qthin = o->q_brem + o->eta * o->q_syn;
   const double T2 = T_e * T_e;
   const double ta = H * qthin / (4.0 * kSigmaSB * T2 * T2);
   const double ts = 2.0 * n_e * kSigmaT * H;
   const bool off = T_e + T_i < floor_gas;
-  o->q_rad = (off || T_e < P.T_floor) ? 0.0 : qthin / (1.0 + kSqrt3 * ta + 1.5 * ta * (ta + ts));
-  o->q_cc = (T_i - T_e) * exp(ln_coulomb_coeff(n_e, T_e, T_i, P.ln_lambda));
+  const bool cooling = !off && T_e >= P.T_floor;
+  const bool no_rate = cooling && !(o->eta > 0.0 && isfinite(o->eta));
+  o->q_rad = !cooling ? 0.0 : no_rate ? __builtin_nan("") : qthin / (1.0 + kSqrt3 * ta + 1.5 * ta * (ta + ts));
+  o->q_cc = (T_i - T_e) * exp(ln_coulomb_coeff(n_e, T_e, T_i, P.ln_lambda, P.theta_i_me != 0));
   o->T_e_new = T_e;
   o->T_i_new = T_i;
-  o->status = off ? ST_GAS_FLOOR : 0;
+  o->status = (off ? ST_GAS_FLOOR : 0) | (no_rate ? ST_NO_RATE : 0);
 }
 
 }  // namespace rc

@@ -19,7 +19,7 @@ namespace rc {
 RC_HD double node_total(double H, double B, double n_e, double T) {
   const double N = n_e * H;
   double ys, ye;
-  node_synch_eta(N, T, B, &ys, &ye);
+  node_synch_eta(N, T, B, false, &ys, &ye);
   const double lH = log2(H);
   const double lb = node_brem(N, T) - 2.0 * lH;           // log2 Q_brem
   const double ls = ys + ye - lH;                           // log2 (eta Q_syn)

@@ -161,8 +161,8 @@ __global__ __launch_bounds__(256, RC_NEWTON_WAVES) void k_newton_first(Tab tab, 
   cs.newton_begin(s0, ns);
   const bool done = cs.newton_round(ns, &r);
   if (diag) cs.diagnostics(s0, &r);
-  if (o.Q_rad) o.Q_rad[i] = r.q_rad;
-  if (o.Q_cc) o.Q_cc[i] = r.q_cc;
+  if (o.Q_rad) put_rate(o.Q_rad, o.rates_f32, i, r.q_rad);
+  if (o.Q_cc) put_rate(o.Q_cc, o.rates_f32, i, r.q_cc);
   if (o.Q_brem) o.Q_brem[i] = r.q_brem;
   if (o.Q_syn) o.Q_syn[i] = r.q_syn;
   if (o.eta) o.eta[i] = r.eta;
@@ -281,7 +281,13 @@ rc_status make_params(rc_tables t, double dt, const rc_step_opts* o, StepParams*
     return set_error(RC_EINVAL, "block must be 0 or a multiple of 64 in [64, 256]");
   if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(RC_EINVAL, "dt must be finite and > 0");
   if (o->passes < 0 || o->passes > 2) return set_error(RC_EINVAL, "passes must be 0, 1 or 2");
+  if (o->grid < 0 || o->grid > RC_MAX_GRID) return set_error(RC_EINVAL, "grid must lie in [0, RC_MAX_GRID]");
+  if (o->rate_dtype != RC_RATE_F64 && o->rate_dtype != RC_RATE_F32)
+    return set_error(RC_EINVAL, "rate_dtype must be RC_RATE_F64 or RC_RATE_F32");
   if (o->reserved != 0) return set_error(RC_EINVAL, "reserved option field must be 0");
+  if (t->spec.compton_exponent == RC_COMPTON_LITERAL && o->scheme != RC_SCHEME_RATES)
+    return set_error(RC_EUNSUPPORTED, "tables of the literal Compton exponent serve the rates scheme only: "
+                                      "eta has no value wherever P A > 1, so no energy update is defined there");
   if (host) {
     fill_geom(t);
     P->g = &t->geom;
@@ -297,6 +303,8 @@ rc_status make_params(rc_tables t, double dt, const rc_step_opts* o, StepParams*
   P->ln_lambda = t->spec.ln_lambda;
   P->max_iter = o->max_iter;
   P->scheme = o->scheme;
+  P->compton_literal = t->spec.compton_exponent == RC_COMPTON_LITERAL ? 1 : 0;
+  P->theta_i_me = t->spec.theta_i_mass == RC_THETA_I_ME ? 1 : 0;
   return RC_OK;
 }
 
@@ -330,7 +338,7 @@ extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n,
   if (hipGetDevice(&dev) != hipSuccess || dev != t->device)
     return set_error(RC_ESTATE, "rc_cool_step: tables live on another device than the current one");
   StateArgs s{state->n_e, state->T_e, state->T_i, state->B, state->H, state->T_floor_gas};
-  OutArgs o{out->T_e_new, out->T_i_new, out->Q_rad, out->Q_cc, out->Q_brem, out->Q_syn, out->eta, out->status};
+  const OutArgs o = out_args(out, opts);
   // library choice: one-wavefront workgroups for the Newton solve (measured
   // fastest: a workgroup retires as soon as its slowest cell is done), 256
   // threads for the single-evaluation schemes

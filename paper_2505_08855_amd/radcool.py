@@ -18,7 +18,7 @@ STATUS_NAMES = {-1: "RC_EINVAL", -2: "RC_ENOMEM", -3: "RC_EDEVICE", -4: "RC_EUNS
                 -5: "RC_ESTATE", -6: "RC_EIO"}
 
 TAB_BREM, TAB_SYNCH, TAB_ETA, TAB_COUL = 0, 1, 2, 3
-ST_INVALID, ST_CLAMP_COOL, ST_CLAMP_COUL, ST_FLOOR, ST_MAXITER, ST_GAS_FLOOR = 1, 2, 4, 8, 16, 32
+ST_INVALID, ST_CLAMP_COOL, ST_CLAMP_COUL, ST_FLOOR, ST_MAXITER, ST_GAS_FLOOR, ST_NO_RATE = 1, 2, 4, 8, 16, 32, 64
 SCHEME_NEWTON, SCHEME_EXPLICIT16, SCHEME_RATES = 0, 1, 2
 VARIANT_AUTO, VARIANT_GLOBAL, VARIANT_LDS, VARIANT_TEX, VARIANT_DIRECT = 0, 1, 2, 3, 4
 VARIANTS = {"auto": 0, "global": 1, "lds": 2, "tex": 3, "direct": 4, "cell": 5}
@@ -33,7 +33,7 @@ EXPORTED = ("rc_default_spec", "rc_default_opts", "rc_build_tables", "rc_tables_
             "rc_disk_inputs", "rc_rad_pressure_correction", "rc_selftest_disk_host", "rc_selftest_radp_host",
             "rc_paper_axes4", "rc_build_table4d", "rc_table4d_import", "rc_table4d_export", "rc_table4d_destroy",
             "rc_rates4d", "rc_selftest_node4d_host", "rc_selftest_rates4d_host", "rc_apply_cooling",
-            "rc_selftest_coupling_host")
+            "rc_selftest_coupling_host", "rc_batched_workgroup_items", "rc_plan_workgroup_items")
 MAX_STATES = 64
 
 
@@ -48,11 +48,15 @@ class Axes(ctypes.Structure):
 
 
 VALUE_DTYPES = {"f32": 0, "bf16": 1}
+COMPTON = {"derived": 0, "literal": 1}
+THETA_I_MASS = {"m_p": 0, "m_e": 1}
+RATE_DTYPES = {"f64": 0, "f32": 1}
 
 
 class TableSpec(ctypes.Structure):
     _fields_ = [("cool", Axes), ("coul", Axes), ("ln_lambda", ctypes.c_double),
-                ("value_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("value_dtype", ctypes.c_int32), ("compton_exponent", ctypes.c_int32),
+                ("theta_i_mass", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class State(ctypes.Structure):
@@ -106,7 +110,8 @@ BLOCK_DTYPE = np.dtype([("first_cell", np.int64), ("n_cells", np.int32), ("state
 class StepOpts(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("variant", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("T_floor", ctypes.c_double), ("tol", ctypes.c_double),
-                ("passes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("passes", ctypes.c_int32), ("grid", ctypes.c_int32), ("rate_dtype", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -146,6 +151,8 @@ def lib():
             "rc_plan_launch": (i32, [vp, vp]),
             "rc_plan_info": (i32, [vp, P(i32), P(i32), P(dbl)]),
             "rc_plan_destroy": (i32, [vp]),
+            "rc_batched_workgroup_items": (i32, [vp, vp, i32, P(i32)]),
+            "rc_plan_workgroup_items": (i32, [vp, vp, i32, P(i32)]),
             "rc_disk_inputs": (i32, [vp, vp, vp, vp, i64, P(DiskParams), vp, vp, vp]),
             "rc_rad_pressure_correction": (i32, [vp, vp, vp, i64, dbl, vp, vp, vp]),
             "rc_selftest_disk_host": (i32, [vp, vp, vp, vp, i64, P(DiskParams), vp, vp]),
@@ -174,15 +181,19 @@ def check(code):
         raise RadcoolError(code, lib().rc_last_error().decode())
 
 
-def default_spec(n=64, value_dtype="f32"):
-    """Default axes with n nodes each; value_dtype 'f32' or 'bf16' residual storage."""
+def default_spec(n=64, value_dtype="f32", compton="derived", theta_i_mass="m_p"):
+    """Default axes with n nodes each; value_dtype 'f32' or 'bf16' residual
+    storage; compton 'derived' or 'literal' (the printed exponent); theta_i_mass
+    'm_p' or 'm_e' (the printed theta_i)."""
     s = TableSpec()
     check(lib().rc_default_spec(ctypes.byref(s), n))
     s.value_dtype = VALUE_DTYPES[value_dtype]
+    s.compton_exponent = COMPTON[compton]
+    s.theta_i_mass = THETA_I_MASS[theta_i_mass]
     return s
 
 
-def spec_from_axes(cool, coul, ln_lambda=20.0, value_dtype="f32"):
+def spec_from_axes(cool, coul, ln_lambda=20.0, value_dtype="f32", compton="derived", theta_i_mass="m_p"):
     """Build a TableSpec from two sequences of (n, lo, hi) triples."""
     s = TableSpec()
     for dst, src in ((s.cool, cool), (s.coul, coul)):
@@ -192,6 +203,8 @@ def spec_from_axes(cool, coul, ln_lambda=20.0, value_dtype="f32"):
             dst.hi[k] = float(hi)
     s.ln_lambda = ln_lambda
     s.value_dtype = VALUE_DTYPES[value_dtype]
+    s.compton_exponent = COMPTON[compton]
+    s.theta_i_mass = THETA_I_MASS[theta_i_mass]
     return s
 
 
@@ -203,6 +216,8 @@ def default_opts(**kw):
             v = SCHEMES[v]
         if k == "variant" and isinstance(v, str):
             v = VARIANTS[v]
+        if k == "rate_dtype" and isinstance(v, str):
+            v = RATE_DTYPES[v]
         setattr(o, k, v)
     return o
 
@@ -292,6 +307,22 @@ class Tables:
             pass
 
 
+def _check_out(out, n, opts):
+    """Output tensors must match the kernels' element types and the cell count."""
+    import torch
+    rt = torch.float32 if opts.rate_dtype == RATE_DTYPES["f32"] else torch.float64
+    want = {"T_e_new": torch.float64, "T_i_new": torch.float64, "Q_rad": rt, "Q_cc": rt, "status": torch.uint8,
+            "Q_brem": torch.float64, "Q_syn": torch.float64, "eta": torch.float64}
+    for k, t in out.items():
+        if t is None:
+            continue
+        if k not in want:
+            raise ValueError("unknown output %s" % k)
+        if t.dtype != want[k] or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+            raise ValueError("output %s must be a contiguous %s HIP tensor of %d elements" % (k, want[k], n))
+    return out
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()
 
@@ -320,11 +351,14 @@ def cool_step(tables, state, dt, opts=None, out=None, diagnostics=False, stream=
     opts = opts or default_opts()
     dev = state["n_e"].device
     if out is None:
-        out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")}
+        rt = torch.float32 if opts.rate_dtype == RATE_DTYPES["f32"] else torch.float64
+        out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("T_e_new", "T_i_new")}
+        out.update({k: torch.empty(n, dtype=rt, device=dev) for k in ("Q_rad", "Q_cc")})
         out["status"] = torch.empty(n, dtype=torch.uint8, device=dev)
         if diagnostics:
             for k in ("Q_brem", "Q_syn", "eta"):
                 out[k] = torch.empty(n, dtype=torch.float64, device=dev)
+    _check_out(out, n, opts)
     st = _state(state)
     o = Out(*[out[k].data_ptr() if out.get(k) is not None else None
               for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc", "status", "Q_brem", "Q_syn", "eta")])
@@ -368,9 +402,11 @@ def _out_struct(out):
                  for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc", "status", "Q_brem", "Q_syn", "eta")])
 
 
-def _alloc_out(n, dev):
+def _alloc_out(n, dev, opts):
     import torch
-    out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")}
+    rt = torch.float32 if opts.rate_dtype == RATE_DTYPES["f32"] else torch.float64
+    out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("T_e_new", "T_i_new")}
+    out.update({k: torch.empty(n, dtype=rt, device=dev) for k in ("Q_rad", "Q_cc")})
     out["status"] = torch.empty(n, dtype=torch.uint8, device=dev)
     return out
 
@@ -380,13 +416,27 @@ def cool_step_batched(tables, state, blocks_dev, n_blocks, dt_per_state, opts=No
     with one dt per accretion state."""
     n = _check_state(state)
     opts = opts or default_opts()
-    out = out if out is not None else _alloc_out(n, state["n_e"].device)
+    out = _check_out(out if out is not None else _alloc_out(n, state["n_e"].device, opts), n, opts)
     dts = np.ascontiguousarray(dt_per_state, dtype=np.float64)
     st = _state(state)
     check(lib().rc_cool_step_batched(tables.handle, ctypes.byref(st), n, ctypes.c_void_p(blocks_dev.data_ptr()),
                                      n_blocks, dts.ctypes.data_as(ctypes.c_void_p), dts.size, ctypes.byref(opts),
                                      ctypes.byref(_out_struct(out)), _stream_ptr(stream)))
     return out
+
+
+def _workgroup_items(fn, handle):
+    g = ctypes.c_int32()
+    check(fn(handle, None, 0, ctypes.byref(g)))
+    items = np.zeros(g.value, dtype=np.uint32)
+    check(fn(handle, items.ctypes.data_as(ctypes.c_void_p), g.value, ctypes.byref(g)))
+    return items
+
+
+def batched_workgroup_items(tables):
+    """Work items each workgroup of the last cool_step_batched launch on these
+    tables took from the queue (waits for the device)."""
+    return _workgroup_items(lib().rc_batched_workgroup_items, tables.handle)
 
 
 class Plan:
@@ -396,7 +446,8 @@ class Plan:
                  stream=None):
         n = _check_state(state)
         self.opts = opts or default_opts()
-        self.out = out if out is not None else _alloc_out(n, state["n_e"].device)
+        self.out = _check_out(out if out is not None else _alloc_out(n, state["n_e"].device, self.opts), n,
+                              self.opts)
         self._keep = (tables, state, blocks_dev)      # the plan holds pointers into these
         dts = np.ascontiguousarray(dt_per_state, dtype=np.float64)
         st = _state(state)
@@ -415,6 +466,10 @@ class Plan:
         b, g, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         check(lib().rc_plan_info(self._h, ctypes.byref(b), ctypes.byref(g), ctypes.byref(ms)))
         return {"block": b.value, "grid": g.value, "tuned_ms": ms.value}
+
+    def workgroup_items(self):
+        """Work items each workgroup of the plan's last launch took (waits for the device)."""
+        return _workgroup_items(lib().rc_plan_workgroup_items, self._h)
 
     def destroy(self):
         if self._h:

@@ -114,10 +114,80 @@ def test_selftest_argument_checks(L):
                                        ctypes.byref(R.default_opts()), None, None, None, None, None) == -1
     assert L.rc_selftest_step_host(ctypes.byref(s), P(resid), P(co), *[P(x)] * 5, None, 1, 1e-8,
                                    ctypes.byref(op), None, None, None, None, None) == -1
-    for field, val in (("scheme", 7), ("variant", 9), ("T_floor", -1.0), ("tol", 0.0), ("block", 96)):
+    for field, val in (("scheme", 7), ("variant", 9), ("T_floor", -1.0), ("tol", 0.0), ("block", 96),
+                       ("rate_dtype", 2), ("reserved", 1), ("grid", -1), ("grid", 65537), ("passes", 3)):
         op = R.default_opts(**{field: val})
         assert L.rc_selftest_step_host(ctypes.byref(s), P(resid), P(co), *[P(x)] * 5, None, 1, 1e-8,
                                        ctypes.byref(op), None, None, None, None, None) == -1, field
+
+
+def test_reading_switches_are_checked(L):
+    """Spec fields outside their enums are rejected; tables of the literal
+    Compton exponent refuse every scheme but the rates."""
+    h = ctypes.c_void_p()
+    for field, val in (("compton_exponent", 2), ("theta_i_mass", -1), ("reserved", 3), ("value_dtype", 5)):
+        bad = R.default_spec(8)
+        setattr(bad, field, val)
+        assert L.rc_build_tables(ctypes.byref(bad), None, ctypes.byref(h)) == -1, field
+        assert not h.value
+    lit = R.default_spec(8, compton="literal")
+    x = np.ones(1)
+    resid = np.zeros(4 * 512, dtype=np.float32)
+    co = np.zeros(16)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    for scheme in ("newton", "explicit16"):
+        assert L.rc_selftest_step_host(ctypes.byref(lit), P(resid), P(co), *[P(x)] * 5, None, 1, 1e-8,
+                                       ctypes.byref(R.default_opts(scheme=scheme)), None, None, None, None,
+                                       None) == -4, scheme
+    assert b"literal Compton" in L.rc_last_error()
+
+
+LAYOUT_C = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "radcool.h"
+#define S(T) printf(#T " size %zu\n", sizeof(T))
+#define O(T, f) printf(#T " " #f " %zu\n", offsetof(T, f))
+int main(void) {
+  S(rc_axes); S(rc_table_spec); S(rc_state); S(rc_out); S(rc_step_opts); S(rc_block); S(rc_fwd);
+  S(rc_cotangent); S(rc_grad); S(rc_disk_params); S(rc_coupling); S(rc_axes4);
+  O(rc_table_spec, ln_lambda); O(rc_table_spec, value_dtype); O(rc_table_spec, compton_exponent);
+  O(rc_table_spec, theta_i_mass); O(rc_table_spec, reserved);
+  O(rc_step_opts, T_floor); O(rc_step_opts, tol); O(rc_step_opts, passes); O(rc_step_opts, grid);
+  O(rc_step_opts, rate_dtype); O(rc_step_opts, reserved);
+  O(rc_out, Q_rad); O(rc_out, status); O(rc_out, eta);
+  O(rc_block, n_cells); O(rc_block, state_id);
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's sizes
+    and field offsets (gcc, the header compiled as C)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "layout.c"
+    src.write_text(LAYOUT_C)
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    lines = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    types = {"rc_axes": R.Axes, "rc_table_spec": R.TableSpec, "rc_state": R.State, "rc_out": R.Out,
+             "rc_step_opts": R.StepOpts, "rc_block": R.Block, "rc_fwd": R.Fwd, "rc_cotangent": R.Cotangent,
+             "rc_grad": R.Grad, "rc_disk_params": R.DiskParams, "rc_coupling": R.Coupling, "rc_axes4": R.Axes4}
+    seen = 0
+    for ln in lines:
+        parts = ln.split()
+        if len(parts) == 3 and parts[1] == "size":
+            assert ctypes.sizeof(types[parts[0]]) == int(parts[2]), parts[0]
+            seen += 1
+        elif len(parts) == 3:
+            assert getattr(types[parts[0]], parts[1]).offset == int(parts[2]), (parts[0], parts[1])
+            seen += 1
+    assert seen == 12 + 16
 
 
 def test_apply_cooling_rejects_bad_arguments(L):

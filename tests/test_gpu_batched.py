@@ -82,6 +82,19 @@ def test_batched_against_oracle_samples(dev, problem):
             assert np.max(rel_err(out[k].cpu().numpy()[idx], ref[k])) < 1e-9, (s, k)
 
 
+def test_queue_loop_takes_many_items_per_workgroup(dev, problem):
+    """More work items than workgroups: the 384 (block, state) items on 16
+    workgroups, so the persistent loop hands each workgroup about 24 items.
+    The per-workgroup counts come back from the kernel itself."""
+    ref = eager_reference(problem, dev)
+    out = R.cool_step_batched(problem["tables"], problem["state"], problem["bdev"], problem["nb"], problem["dts"],
+                              R.default_opts(grid=16))
+    items = R.batched_workgroup_items(problem["tables"])
+    assert items.size == 16 and int(items.sum()) == problem["nb"]
+    assert items.max() >= 2 and int((items >= 2).sum()) >= 12, items
+    close(out, ref)
+
+
 def test_plan_graph_replays(dev, problem):
     ref = eager_reference(problem, dev)
     plan = R.Plan(problem["tables"], problem["state"], problem["bdev"], problem["nb"], problem["dts"])

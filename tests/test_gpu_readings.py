@@ -1,0 +1,200 @@
+"""GPU parity of the selectable readings and the FP32 rate outputs.
+
+* Literal Compton exponent (paper II.C as printed): GPU-built tables hold no
+  value at exactly the oracle's nodes; the rates scheme flags exactly the
+  oracle's cells (RC_ST_NO_RATE, Q_rad = NaN) and matches the rates tier
+  elsewhere; the DIRECT variant flags the cells where eta <= 0 and matches
+  the closed forms to 1e-9; energy updates, the batched form and the adjoint
+  refuse such tables.
+* Printed theta_i = k T_i / m_e c^2 (paper II.G): the GPU build against the
+  oracle's table of that reading (node tier), the rates tier, and the energy
+  tier of the Newton step on identical (imported) table data.
+* FP32 rate outputs: every scheme writes Q_rad and Q_cc as the FP64 values
+  rounded to nearest float (bit for bit), T' unchanged.
+"""
+import numpy as np
+import pytest
+
+from conftest import rel_err
+from oracle import constants as K
+from oracle import physics as P
+from oracle import step as S
+from oracle import tables as T
+from paper_2505_08855_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+R = pytest.importorskip("paper_2505_08855_amd.radcool")
+DT = W.DT_DEFAULT
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def cells0():
+    return W.workload(0)
+
+
+def to_dev(cells, dev, idx=None):
+    return {k: torch.from_numpy(np.ascontiguousarray(cells[k] if idx is None else cells[k][idx])).to(dev)
+            for k in W.FIELDS}
+
+
+def to_np(out):
+    return {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+
+
+def reconstruct(gt, spec):
+    resid, coeffs = gt.export()
+    vc = spec.cool.n[0] * spec.cool.n[1] * spec.cool.n[2]
+    out = {}
+    for k, name in enumerate(T.TABLE_NAMES):
+        ax = spec.coul if k == 3 else spec.cool
+        shape = tuple(ax.n)
+        r = resid[k * vc: k * vc + int(np.prod(shape))].reshape(shape).astype(np.float64)
+        g = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
+        out[name] = coeffs[k, 0] + coeffs[k, 1] * g[0] + coeffs[k, 2] * g[1] + coeffs[k, 3] * g[2] + r
+    return out
+
+
+# ------------------------------------------------------------------ literal Compton exponent
+
+
+@pytest.fixture(scope="module")
+def literal(dev):
+    spec = T.TableSpec.default(64, compton="literal")
+    return spec, T.build_tables(spec), R.Tables.build(R.default_spec(64, compton="literal"))
+
+
+def test_literal_nodes_without_value_match(literal):
+    spec, tabs, gt = literal
+    got = reconstruct(gt, R.default_spec(64, compton="literal"))
+    holes = np.isnan(tabs["eta"])
+    assert holes.any()
+    assert np.array_equal(np.isnan(got["eta"]), holes)
+    for name in T.TABLE_NAMES:
+        ok = ~np.isnan(tabs[name])
+        assert np.max(np.abs(got[name][ok] - tabs[name][ok])) < 1.44e-6, name
+
+
+@pytest.mark.parametrize("variant", ["auto", "global", "lds"])
+def test_literal_rates_status_and_tier(dev, literal, cells0, variant):
+    spec, tabs, gt = literal
+    out = to_np(R.cool_step(gt, to_dev(cells0, dev), DT, R.default_opts(scheme="rates", variant=variant)))
+    ref = S.table_rates(S.TableSet(spec, tabs), *[cells0[f] for f in W.FIELDS])
+    assert np.array_equal(out["status"], ref["status"])
+    flagged = (ref["status"] & S.ST_NO_RATE) != 0
+    assert 0.05 < flagged.mean() < 0.6
+    assert np.array_equal(np.isnan(out["Q_rad"]), flagged)
+    ok = ~flagged
+    assert np.max(rel_err(out["Q_rad"][ok], ref["q_rad"][ok])) < 1e-5
+    assert np.max(rel_err(out["Q_cc"], ref["q_cc"])) < 1e-5
+
+
+def test_literal_direct_variant(dev, literal, cells0):
+    idx = np.arange(0, 32768, 8)
+    gt = literal[2]
+    out = to_np(R.cool_step(gt, to_dev(cells0, dev, idx), DT, R.default_opts(scheme="rates", variant="direct"),
+                            diagnostics=True))
+    ref = P.direct_rates(*[cells0[f][idx] for f in W.FIELDS], compton="literal")
+    flagged = ~(ref["eta"] > 0) & (cells0["T_e"][idx] >= 1e6)
+    assert flagged.any()
+    assert np.array_equal((out["status"] & R.ST_NO_RATE) != 0, flagged)
+    assert np.array_equal(np.isnan(out["Q_rad"]), flagged)
+    assert np.max(np.abs(out["eta"] - ref["eta"]) / np.maximum(np.abs(ref["eta"]), 1.0)) < 1e-9
+    ok = ~flagged
+    assert np.max(rel_err(out["Q_rad"][ok], ref["q_rad"][ok])) < 1e-9
+
+
+def test_literal_tables_refuse_energy_updates(dev, literal, cells0):
+    gt = literal[2]
+    st = to_dev(cells0, dev, np.arange(64))
+    for scheme in ("newton", "explicit16"):
+        with pytest.raises(R.RadcoolError) as e:
+            R.cool_step(gt, st, DT, R.default_opts(scheme=scheme))
+        assert e.value.code == -4
+    with pytest.raises(R.RadcoolError) as e:
+        R.cool_step_backward(gt, st, DT, None, {}, R.default_opts(scheme="rates"))
+    assert e.value.code == -4
+
+
+# ------------------------------------------------------------------ printed theta_i
+
+
+@pytest.fixture(scope="module")
+def theta_me(dev):
+    spec = T.TableSpec.default(64, theta_i_mass="m_e")
+    return spec, T.build_tables(spec)
+
+
+def test_theta_i_me_build_and_rates(dev, theta_me, cells0):
+    spec, tabs = theta_me
+    gt = R.Tables.build(R.default_spec(64, theta_i_mass="m_e"))
+    got = reconstruct(gt, R.default_spec(64, theta_i_mass="m_e"))
+    for name in T.TABLE_NAMES:
+        assert np.max(np.abs(got[name] - tabs[name])) < 1.44e-6, name
+    out = to_np(R.cool_step(gt, to_dev(cells0, dev), DT, R.default_opts(scheme="rates")))
+    ref = S.table_rates(S.TableSet(spec, tabs), *[cells0[f] for f in W.FIELDS])
+    assert np.max(rel_err(out["Q_cc"], ref["q_cc"])) < 1e-5
+    assert np.max(rel_err(out["Q_rad"], ref["q_rad"])) < 1e-5
+    assert np.array_equal(out["status"], ref["status"])
+    # the reading matters: the default Coulomb coefficient differs by orders of magnitude
+    d = to_np(R.cool_step(R.Tables.build(R.default_spec(64)), to_dev(cells0, dev), DT,
+                          R.default_opts(scheme="rates")))
+    assert np.median(rel_err(out["Q_cc"], d["Q_cc"])) > 1.0
+    # DIRECT on these tables takes the same reading
+    idx = np.arange(0, 32768, 16)
+    dd = to_np(R.cool_step(gt, to_dev(cells0, dev, idx), DT, R.default_opts(scheme="rates", variant="direct")))
+    qc = P.q_coulomb(cells0["n_e"][idx], cells0["T_e"][idx], cells0["T_i"][idx], theta_i_mass=K.M_E)
+    assert np.max(rel_err(dd["Q_cc"], qc)) < 1e-9
+
+
+def test_theta_i_me_energy_tier(dev, theta_me, cells0):
+    spec, tabs = theta_me
+    co, re, stored = T.quantize_tables(tabs)
+    resid = np.concatenate([re[k].ravel() for k in T.TABLE_NAMES])
+    coeffs = np.stack([co[k] for k in T.TABLE_NAMES])
+    gt = R.Tables.from_storage(R.default_spec(64, theta_i_mass="m_e"), resid, coeffs)
+    idx = np.arange(0, 32768, 16)
+    out = to_np(R.cool_step(gt, to_dev(cells0, dev, idx), DT))
+    ref = S.step_be(S.TableSet(spec, stored), *[cells0[f][idx] for f in W.FIELDS], DT)
+    for k in ("T_e_new", "T_i_new"):
+        assert np.max(rel_err(out[k], ref[k])) < 1e-9, k
+
+
+# ------------------------------------------------------------------ FP32 rate outputs
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(passes=1), dict(scheme="rates"), dict(scheme="explicit16"),
+                                dict(scheme="rates", variant="direct")])
+def test_f32_rates_are_rounded_fp64_rates(dev, cells0, kw):
+    gt = R.Tables.build(R.default_spec(64))
+    st = to_dev(cells0, dev)
+    a = R.cool_step(gt, st, DT, R.default_opts(**kw))
+    b = R.cool_step(gt, st, DT, R.default_opts(rate_dtype="f32", **kw))
+    assert b["Q_rad"].dtype == torch.float32 and b["Q_cc"].dtype == torch.float32
+    for k in ("Q_rad", "Q_cc"):
+        assert torch.equal(b[k], a[k].float()), k
+    for k in ("T_e_new", "T_i_new", "status"):
+        assert torch.equal(b[k], a[k]), k
+
+
+def test_f32_rates_batched(dev, cells0):
+    gt = R.Tables.build(R.default_spec(64))
+    st = to_dev(cells0, dev)
+    blocks = [(k * 512, 512, k % 3) for k in range(64)]
+    bdev, nb = R.blocks_to_device(blocks, dev)
+    dts = [DT, 2 * DT, 3 * DT]
+    a = R.cool_step_batched(gt, st, bdev, nb, dts)
+    b = R.cool_step_batched(gt, st, bdev, nb, dts, R.default_opts(rate_dtype="f32"))
+    for k in ("Q_rad", "Q_cc"):
+        assert b[k].dtype == torch.float32 and torch.equal(b[k], a[k].float()), k
+    assert torch.equal(a["T_e_new"], b["T_e_new"])
+    with pytest.raises(ValueError):
+        R.cool_step(gt, st, DT, R.default_opts(rate_dtype="f32"), out=a)   # FP64 buffers for FP32 rates
