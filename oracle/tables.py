@@ -167,7 +167,9 @@ def quantize(y, value_dtype="f32"):
     interpolation reproduces the affine part exactly, so only the residual is
     rounded; its magnitude is what sets the storage error.
     """
-    coeffs = affine_fit(y)
+    # a table with nodes that hold no value (NaN: the literal Compton reading)
+    # keeps a zero affine part, so its residual is the log2 value itself
+    coeffs = np.zeros(4) if np.isnan(y).any() else affine_fit(y)
     grids = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in y.shape], indexing="ij")
     base = affine_eval(coeffs, *grids)
     resid = (y - base).astype(np.float32)

@@ -1,11 +1,13 @@
 """GPU parity of the selectable readings and the FP32 rate outputs.
 
 * Literal Compton exponent (paper II.C as printed): GPU-built tables hold no
-  value at exactly the oracle's nodes; the rates scheme flags exactly the
-  oracle's cells (RC_ST_NO_RATE, Q_rad = NaN) and matches the rates tier
-  elsewhere; the DIRECT variant flags the cells where eta <= 0 and matches
-  the closed forms to 1e-9; energy updates, the batched form and the adjoint
-  refuse such tables.
+  value at the oracle's nodes wherever eta is significant (|eta| >= 1e-6;
+  below that the printed formula cancels to rounding noise, whose sign is not
+  determined); on identical (imported) table data the rates scheme flags
+  exactly the oracle's cells (RC_ST_NO_RATE, Q_rad = NaN) and matches the
+  rates tier elsewhere; the DIRECT variant flags the cells where a significant
+  eta is <= 0 and matches the closed forms to 1e-9; energy updates, the
+  batched form and the adjoint refuse such tables.
 * Printed theta_i = k T_i / m_e c^2 (paper II.G): the GPU build against the
   oracle's table of that reading (node tier), the rates tier, and the energy
   tier of the Newton step on identical (imported) table data.
@@ -72,22 +74,55 @@ def literal(dev):
     return spec, T.build_tables(spec), R.Tables.build(R.default_spec(64, compton="literal"))
 
 
+def literal_eta_nodes(spec):
+    """The printed-exponent eta at every cooling node (linear value, sign kept)."""
+    uN, uT, uB = np.meshgrid(*(a.nodes() for a in spec.cool), indexing="ij")
+    N, Te, B = 10.0 ** uN, 10.0 ** uT, 10.0 ** uB
+    one = np.ones_like(N)
+    return P.compton_eta_printed(N, Te, one, P.synchrotron(N, Te, B, one)["nu_c"])
+
+
+# Where P A > 1 the printed formula is 1 + a b with a b close to -1, and eta is
+# what is left of that cancellation: at |eta| below about 1e-12 it is rounding
+# noise (values of either sign, a few 1e-13, at neighbouring nodes), so its sign
+# and value there depend on the last bits of the node coordinates and of the
+# elementary functions, which differ between the GPU build and the oracle.
+# Nodes with |eta| < 1e-6 (relative noise above 1e-7) are compared only for
+# having no significant value: NaN, or a value below 1e-5.
+ETA_NOISE = 1e-6
+
+
 def test_literal_nodes_without_value_match(literal):
     spec, tabs, gt = literal
     got = reconstruct(gt, R.default_spec(64, compton="literal"))
     holes = np.isnan(tabs["eta"])
     assert holes.any()
-    assert np.array_equal(np.isnan(got["eta"]), holes)
+    noisy = np.abs(literal_eta_nodes(spec)) < ETA_NOISE
+    assert noisy.mean() < 0.2
+    firm = ~noisy
+    assert np.array_equal(np.isnan(got["eta"])[firm], holes[firm])
+    assert (holes & firm).sum() > 0.5 * holes.sum()
+    g = got["eta"][noisy]
+    assert np.all(np.isnan(g) | (g < np.log2(1e-5)))
     for name in T.TABLE_NAMES:
-        ok = ~np.isnan(tabs[name])
-        assert np.max(np.abs(got[name][ok] - tabs[name][ok])) < 1.44e-6, name
+        ok = ~np.isnan(tabs[name]) & (firm if name == "eta" else True)
+        # a table with value-less nodes keeps a zero affine part: its FP32
+        # residual is the log2 value itself, rounded to half an FP32 ulp of it
+        tol = 1.44e-6 + np.abs(tabs[name][ok]) * 2.0 ** -24
+        assert np.all(np.abs(got[name][ok] - tabs[name][ok]) < tol), name
 
 
 @pytest.mark.parametrize("variant", ["auto", "global", "lds"])
 def test_literal_rates_status_and_tier(dev, literal, cells0, variant):
-    spec, tabs, gt = literal
+    # the oracle's tables imported in storage form, so that both sides hold
+    # the same value-less nodes (their sign is rounding noise at some nodes)
+    spec, tabs, _ = literal
+    co, re, stored = T.quantize_tables(tabs)
+    gt = R.Tables.from_storage(R.default_spec(64, compton="literal"),
+                               np.concatenate([re[k].ravel() for k in T.TABLE_NAMES]),
+                               np.stack([co[k] for k in T.TABLE_NAMES]))
     out = to_np(R.cool_step(gt, to_dev(cells0, dev), DT, R.default_opts(scheme="rates", variant=variant)))
-    ref = S.table_rates(S.TableSet(spec, tabs), *[cells0[f] for f in W.FIELDS])
+    ref = S.table_rates(S.TableSet(spec, stored), *[cells0[f] for f in W.FIELDS])
     assert np.array_equal(out["status"], ref["status"])
     flagged = (ref["status"] & S.ST_NO_RATE) != 0
     assert 0.05 < flagged.mean() < 0.6
@@ -105,10 +140,12 @@ def test_literal_direct_variant(dev, literal, cells0):
     ref = P.direct_rates(*[cells0[f][idx] for f in W.FIELDS], compton="literal")
     flagged = ~(ref["eta"] > 0) & (cells0["T_e"][idx] >= 1e6)
     assert flagged.any()
-    assert np.array_equal((out["status"] & R.ST_NO_RATE) != 0, flagged)
-    assert np.array_equal(np.isnan(out["Q_rad"]), flagged)
+    firm = np.abs(ref["eta"]) >= ETA_NOISE        # see ETA_NOISE: the sign of a cancelled eta is noise
+    assert firm.mean() > 0.8
+    assert np.array_equal(((out["status"] & R.ST_NO_RATE) != 0)[firm], flagged[firm])
+    assert np.array_equal(np.isnan(out["Q_rad"])[firm], flagged[firm])
     assert np.max(np.abs(out["eta"] - ref["eta"]) / np.maximum(np.abs(ref["eta"]), 1.0)) < 1e-9
-    ok = ~flagged
+    ok = firm & ~flagged
     assert np.max(rel_err(out["Q_rad"][ok], ref["q_rad"][ok])) < 1e-9
 
 
@@ -147,7 +184,7 @@ def test_theta_i_me_build_and_rates(dev, theta_me, cells0):
     # the reading matters: the default Coulomb coefficient differs by orders of magnitude
     d = to_np(R.cool_step(R.Tables.build(R.default_spec(64)), to_dev(cells0, dev), DT,
                           R.default_opts(scheme="rates")))
-    assert np.median(rel_err(out["Q_cc"], d["Q_cc"])) > 1.0
+    assert np.median(np.abs(np.log10(out["Q_cc"] / d["Q_cc"]))) > 1.0
     # DIRECT on these tables takes the same reading
     idx = np.arange(0, 32768, 16)
     dd = to_np(R.cool_step(gt, to_dev(cells0, dev, idx), DT, R.default_opts(scheme="rates", variant="direct")))
