@@ -168,11 +168,17 @@ enum { RC_SCHEME_NEWTON = 0, RC_SCHEME_EXPLICIT16 = 1, RC_SCHEME_RATES = 2 };
  * 256).  It pays only for spatially coherent cell order.  TEX names the texture-memory path
  * of the paper's GPU (Sec. III.A); gfx950 exposes no texture sampling to HIP,
  * so it returns RC_EUNSUPPORTED.  DIRECT evaluates the closed forms of
- * Sec. II per cell instead of tables (rates scheme only).  CELL reads a
+ * Sec. II per cell instead of tables (rates scheme only).  Every variant
+ * reads the synchrotron and Compton tables as their sum se = log2(eta Q_syn)
+ * (they enter the rates only as that product): se's residual at a node is
+ * the single-precision sum of the two stored residuals (one IEEE addition,
+ * rounded to nearest) and its affine part the sum of theirs.  CELL reads a
  * cell-blocked copy of the FP32 tables, the 8 corners of every table cell
- * stored together (a cooling cell's 8 x 16 bytes fill one 128-byte cache
- * line), so that a corner gather touches one line instead of four, for 8
- * times the table memory (about 256 MiB more at 128^3 nodes).  The copy is
+ * stored together (a cooling cell's 8 {brem, se} pairs in one aligned
+ * 64-byte block, a Coulomb cell's 8 values in 32 bytes), so that a corner
+ * gather touches one block instead of four node pairs, for 4 times the
+ * cooling and 8 times the Coulomb table memory (about 200 MiB at 128^3
+ * nodes).  The copy is
  * built on the first CELL (or AUTO) call for an FP32 table set: that call
  * allocates device memory and synchronizes its stream; later calls do
  * neither (make one call before capturing a graph).  Results equal GLOBAL's.

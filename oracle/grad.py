@@ -66,13 +66,14 @@ def qrad_parts(ts, n_e, x, B, H, T_floor):
     ux = np.log10(x)
     uB = np.log10(B)
     yb, dyb, ib, wb = interp_parts(ts.t["brem"], ts.spec.cool, uN, ux, uB)
-    ys, dys, is_, ws = interp_parts(ts.t["synch"], ts.spec.cool, uN, ux, uB)
-    ye, dye, ie, we = interp_parts(ts.t["eta"], ts.spec.cool, uN, ux, uB)
+    # eta Q_syn through the se table (log2 of the product; synch + eta), whose
+    # entries move with either table's: d se / d synch = d se / d eta = 1
+    yse, dyse, ise, wse = interp_parts(ts.t["se"], ts.spec.cool, uN, ux, uB)
     vb = np.exp2(yb) / H ** 2               # Q_brem
-    vse = np.exp2(ys + ye) / H              # eta Q_syn
+    vse = np.exp2(yse) / H                  # eta Q_syn
     qt = vb + vse
     # dQ_thin / du_a (log10 coordinates) and the chain to physical variables
-    dqt_du = [LN2 * (vb * dyb[a] + vse * (dys[a] + dye[a])) for a in range(3)]
+    dqt_du = [LN2 * (vb * dyb[a] + vse * dyse[a]) for a in range(3)]
     dqt = {"n_e": dqt_du[0] / (n_e * LN10),
            "x": dqt_du[1] / (x * LN10),
            "B": dqt_du[2] / (B * LN10),
@@ -93,8 +94,8 @@ def qrad_parts(ts, n_e, x, B, H, T_floor):
         dts = ts_ * ((1.0 / n_e if p == "n_e" else 0.0) + (1.0 / H if p == "H" else 0.0))
         d[p] = fac * dqt[p] - qt / D ** 2 * (D_ta * dta + 1.5 * ta * dts)
     d["tab"] = [("brem", ib, fac[:, None] * LN2 * vb[:, None] * wb),
-                ("synch", is_, fac[:, None] * LN2 * vse[:, None] * ws),
-                ("eta", ie, fac[:, None] * LN2 * vse[:, None] * we)]
+                ("synch", ise, fac[:, None] * LN2 * vse[:, None] * wse),
+                ("eta", ise, fac[:, None] * LN2 * vse[:, None] * wse)]
     off = x < T_floor
     q = np.where(off, 0.0, q)
     for p in ("n_e", "x", "B", "H"):

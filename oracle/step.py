@@ -47,24 +47,30 @@ ST_NO_RATE = 64       # literal Compton reading: a cooling-table corner of the c
 
 
 class TableSet:
-    """FP64 log2 tables plus their axes; evaluates the interpolated quantities."""
+    """FP64 log2 tables plus their axes; evaluates the interpolated quantities.
+
+    ``tables`` may carry "se" (log2 of eta Q_syn; the storage form's own, see
+    oracle.tables.quantize_tables); otherwise se is synch + eta."""
 
     def __init__(self, spec, tables):
         self.spec = spec
         self.t = {k: np.asarray(tables[k], dtype=np.float64) for k in TABLE_NAMES}
+        self.t["se"] = (np.asarray(tables["se"], dtype=np.float64) if "se" in tables
+                        else self.t["synch"] + self.t["eta"])
 
     def cooling(self, n_e, T, B, H):
-        """(v_b, v_s, v_eta, clamped) at column N = n_e H."""
+        """(v_b, v_s, v_eta, v_se, clamped) at column N = n_e H; v_se = eta Q_syn(H = 1)
+        from the se table (the rate path's product)."""
         uN = np.log10(n_e) + np.log10(H)
         uT = np.log10(T)
         uB = np.log10(B)
         out = []
         clamped = False
-        for k in ("brem", "synch", "eta"):
+        for k in ("brem", "synch", "eta", "se"):
             y, c = interp3(self.t[k], self.spec.cool, uN, uT, uB)
             out.append(np.exp2(y))
             clamped = clamped | c
-        return out[0], out[1], out[2], clamped
+        return out[0], out[1], out[2], out[3], clamped
 
     def coulomb(self, n_e, T_e, T_i):
         """(v_c, clamped): the Coulomb coefficient Q_cc / (T_i - T_e)."""
@@ -81,18 +87,18 @@ def bridge(q_thin, T, H, n_e):
 
 def q_rad_at(ts, n_e, T, B, H, T_floor):
     """Bridged radiative cooling at electron temperature T, zero below T_floor."""
-    v_b, v_s, v_eta, _ = ts.cooling(n_e, T, B, H)
-    q_thin = v_b / (H * H) + v_eta * v_s / H
+    v_b, _, _, v_se, _ = ts.cooling(n_e, T, B, H)
+    q_thin = v_b / (H * H) + v_se / H
     return np.where(T < T_floor, 0.0, bridge(q_thin, T, H, n_e))
 
 
 def table_rates(ts, n_e, T_e, T_i, B, H, T_floor=1.0e6):
     """All rates at the input state (dict of arrays) plus a status array."""
     n_e, T_e, T_i, B, H = (np.asarray(v, dtype=np.float64) for v in (n_e, T_e, T_i, B, H))
-    v_b, v_s, v_eta, cl_cool = ts.cooling(n_e, T_e, B, H)
+    v_b, v_s, v_eta, v_se, cl_cool = ts.cooling(n_e, T_e, B, H)
     q_brem = v_b / (H * H)
     q_syn = v_s / H
-    q_thin = q_brem + v_eta * q_syn
+    q_thin = q_brem + v_se / H
     q_rad = np.where(T_e < T_floor, 0.0, bridge(q_thin, T_e, H, n_e))
     v_c, cl_coul = ts.coulomb(n_e, T_e, T_i)
     status = (np.where(cl_cool, ST_CLAMP_COOL, 0) | np.where(cl_coul, ST_CLAMP_COUL, 0) |

@@ -16,6 +16,11 @@ decades, and power laws such as n^2 are then reproduced exactly between nodes):
   synch: log2 Q_syn(N, T_e, B, H = 1)           axes (log10 N, log10 T_e, log10 B)
   eta  : log2 eta(N, T_e, B, H = 1)             axes (log10 N, log10 T_e, log10 B)
   coul : log2(Q_cc / (T_i - T_e))               axes (log10 n_e, log10 T_e, log10 T_i)
+The cooling rate needs synch and eta only as the product eta Q_syn, so the
+rate path reads se = synch + eta = log2(eta Q_syn) as one table.  In FP64 it is
+the sum of the two; in the storage form (below) its residual is the
+single-precision sum of the two stored residuals and its affine part the sum
+of theirs.
 
 Node k of an axis is u_k = lo + k (hi - lo) / (n - 1).  A query coordinate u
 becomes f = (u - lo) / d with d = (hi - lo) / (n - 1), clamped to [0, n - 1];
@@ -181,10 +186,17 @@ def quantize(y, value_dtype="f32"):
 
 
 def quantize_tables(tables, value_dtype="f32"):
-    """Apply ``quantize`` to every table; returns (coeffs dict, resid dict, stored dict)."""
+    """Apply ``quantize`` to every table; returns (coeffs dict, resid dict, stored dict).
+
+    The stored dict also holds "se", the stored form of synch + eta: affine
+    part coeffs[synch] + coeffs[eta], residual the single-precision sum of the
+    two stored residuals (one IEEE addition in float32, rounded to nearest)."""
     co, re, st = {}, {}, {}
     for k in TABLE_NAMES:
         co[k], re[k], st[k] = quantize(tables[k], value_dtype)
+    grids = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in re["synch"].shape], indexing="ij")
+    r_se = np.add(re["synch"], re["eta"], dtype=np.float32)
+    st["se"] = affine_eval(co["synch"] + co["eta"], *grids) + r_se.astype(np.float64)
     return co, re, st
 
 

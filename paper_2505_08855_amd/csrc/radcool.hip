@@ -220,8 +220,9 @@ rc_status upload(rc_tables_s* t, void* stream) {
 }
 
 // cell-blocked copies: corner (a, b, c) of cell (i0, i1, i2) at
-// ((i0 (n1 - 1) + i1) (n2 - 1) + i2) 8 + a 4 + b 2 + c
-__global__ __launch_bounds__(256) void k_cells_cool(const float4* nodes, float4* cells, int n0, int n1, int n2) {
+// ((i0 (n1 - 1) + i1) (n2 - 1) + i2) 8 + a 4 + b 2 + c; the cooling copy holds
+// the solver's {brem, se} pair of each corner
+__global__ __launch_bounds__(256) void k_cells_cool(const float4* nodes, float2* cells, int n0, int n1, int n2) {
   const int64_t total = (int64_t)(n0 - 1) * (n1 - 1) * (n2 - 1) * 8;
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
     const int k = (int)(j & 7);
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(256) void k_cells_cool(const float4* nodes, float4*
     c /= (n2 - 1);
     const int i1 = (int)(c % (n1 - 1));
     const int i0 = (int)(c / (n1 - 1));
-    cells[j] = nodes[((int64_t)(i0 + (k >> 2)) * n1 + i1 + ((k >> 1) & 1)) * n2 + i2 + (k & 1)];
+    cells[j] = brem_se(nodes[((int64_t)(i0 + (k >> 2)) * n1 + i1 + ((k >> 1) & 1)) * n2 + i2 + (k & 1)]);
   }
 }
 
@@ -256,11 +257,11 @@ rc_status ensure_cells(rc_tables_s* t, hipStream_t s) {
   const int64_t nc = (int64_t)(a.n[0] - 1) * (a.n[1] - 1) * (a.n[2] - 1) * 8;
   const int64_t nk = (int64_t)(k.n[0] - 1) * (k.n[1] - 1) * (k.n[2] - 1) * 8;
   void *dc = nullptr, *dk = nullptr;
-  hipError_t e = hipMalloc(&dc, sizeof(float4) * nc);
+  hipError_t e = hipMalloc(&dc, sizeof(float2) * nc);
   if (e == hipSuccess) e = hipMalloc(&dk, sizeof(float) * nk);
   if (e == hipSuccess) {
     const auto grid = [](int64_t m) { return (unsigned)std::min<int64_t>((m + 255) / 256, 1 << 16); };
-    hipLaunchKernelGGL(k_cells_cool, dim3(grid(nc)), dim3(256), 0, s, (const float4*)t->d_cool, (float4*)dc, a.n[0],
+    hipLaunchKernelGGL(k_cells_cool, dim3(grid(nc)), dim3(256), 0, s, (const float4*)t->d_cool, (float2*)dc, a.n[0],
                        a.n[1], a.n[2]);
     hipLaunchKernelGGL(k_cells_coul, dim3(grid(nk)), dim3(256), 0, s, (const float*)t->d_coul, (float*)dk, k.n[0],
                        k.n[1], k.n[2]);

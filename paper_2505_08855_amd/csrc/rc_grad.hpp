@@ -42,7 +42,7 @@ template <class Tab>
 RC_HD CoolPoint cool_point(const Tab& tab, const StepParams& P, double u0, double u1, double u2, int n1, int n2) {
   const Coord c0 = axis_coord(u0, P.g->ax[0]), c1 = axis_coord(u1, P.g->ax[1]), c2 = axis_coord(u2, P.g->ax[2]);
   CoolPoint r;
-  double yb = 0.0, ys = 0.0, ye = 0.0;
+  double yb = 0.0, yse = 0.0;
   double gb[3] = {0.0, 0.0, 0.0}, gse[3] = {0.0, 0.0, 0.0};
   int k = 0;
   for (int a = 0; a < 2; ++a) {
@@ -53,10 +53,10 @@ RC_HD CoolPoint cool_point(const Tab& tab, const StepParams& P, double u0, doubl
         const double wm = m ? c2.t : 1.0 - c2.t, dm = m ? 1.0 : -1.0;
         const float4 p = tab.cool_at(c0.i + a, c1.i + b, c2.i + m);
         const double w = wa * wb * wm;
-        const double vb = p.x, vse = (double)p.y + (double)p.z;
+        const float2 q = brem_se(p);     // the solver's {brem, se} pair
+        const double vb = q.x, vse = q.y;
         yb += w * vb;
-        ys += w * (double)p.y;
-        ye += w * (double)p.z;
+        yse += w * vse;
         const double g0 = da * wb * wm, g1 = wa * db * wm, g2 = wa * wb * dm;
         gb[0] += g0 * vb; gb[1] += g1 * vb; gb[2] += g2 * vb;
         gse[0] += g0 * vse; gse[1] += g1 * vse; gse[2] += g2 * vse;
@@ -72,7 +72,7 @@ RC_HD CoolPoint cool_point(const Tab& tab, const StepParams& P, double u0, doubl
   const double* cs = P.g->coef[1];
   const double* ce = P.g->coef[2];
   r.yb = cb[0] + cb[1] * f0 + cb[2] * f1 + cb[3] * f2 + yb;
-  r.yse = (cs[0] + ce[0]) + (cs[1] + ce[1]) * f0 + (cs[2] + ce[2]) * f1 + (cs[3] + ce[3]) * f2 + ys + ye;
+  r.yse = (cs[0] + ce[0]) + (cs[1] + ce[1]) * f0 + (cs[2] + ce[2]) * f1 + (cs[3] + ce[3]) * f2 + yse;
   const double dfdu[3] = {c0.dfdu, c1.dfdu, c2.dfdu};
   for (int q = 0; q < 3; ++q) {
     r.dyb[q] = (cb[q + 1] + gb[q]) * dfdu[q];

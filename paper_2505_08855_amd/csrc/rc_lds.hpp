@@ -35,7 +35,7 @@ struct LdsTab {
     if constexpr (COUL) return coul_s[((i0 - m0) * g.k1 + i1) * g.k2 + i2];
     else return g.coul_at(i0, i1, i2);
   }
-  __device__ void cool8(int i0, int i1, int i2, float4 (&v)[8]) const { corners8(*this, i0, i1, i2, v); }
+  __device__ void cool8(int i0, int i1, int i2, float2 (&v)[8]) const { corners8se(*this, i0, i1, i2, v); }
   __device__ void coul8(int i0, int i1, int i2, float (&v)[8]) const { corners8c(*this, i0, i1, i2, v); }
 };
 

@@ -106,12 +106,28 @@ RC_HD Coord axis_coord(double u, const AxisP& a) {
 // Table memory in global memory: cooling tables interleaved per node as
 // {brem, synch, eta, 0} (one 16-byte load per corner serves all three), the
 // Coulomb table planar; both C-ordered [i0][i1][i2].
+//
+// The solver reads the cooling tables as two quantities per corner: brem and
+// se = log2(Q_syn eta), the synchrotron and Compton tables summed (they enter
+// the rates only as a product).  se's stored residual is the single-precision
+// sum of the two stored residuals (one IEEE addition, rounded to nearest), its
+// affine part the sum of theirs; every accessor forms it the same way, and
+// the cell-blocked copy stores it.
+RC_HD float2 brem_se(const float4& p) { return make_float2(p.x, p.y + p.z); }
+
 // the 8 corners of the table cell with lowest corner (i0, i1, i2) through an
 // accessor's single-node reads, corner (a, b, c) at a * 4 + b * 2 + c
 template <class T>
 RC_HD void corners8(const T& t, int i0, int i1, int i2, float4 (&v)[8]) {
 #pragma unroll
   for (int k = 0; k < 8; ++k) v[k] = t.cool_at(i0 + (k >> 2), i1 + ((k >> 1) & 1), i2 + (k & 1));
+}
+
+// the same as {brem, se} pairs
+template <class T>
+RC_HD void corners8se(const T& t, int i0, int i1, int i2, float2 (&v)[8]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = brem_se(t.cool_at(i0 + (k >> 2), i1 + ((k >> 1) & 1), i2 + (k & 1)));
 }
 
 template <class T>
@@ -127,7 +143,7 @@ struct GlobalTab {
   int k1, k2;           // Coulomb n1, n2
   RC_HD float4 cool_at(int i0, int i1, int i2) const { return cool[((long)i0 * c1 + i1) * c2 + i2]; }
   RC_HD float coul_at(int i0, int i1, int i2) const { return coul[((long)i0 * k1 + i1) * k2 + i2]; }
-  RC_HD void cool8(int i0, int i1, int i2, float4 (&v)[8]) const { corners8(*this, i0, i1, i2, v); }
+  RC_HD void cool8(int i0, int i1, int i2, float2 (&v)[8]) const { corners8se(*this, i0, i1, i2, v); }
   RC_HD void coul8(int i0, int i1, int i2, float (&v)[8]) const { corners8c(*this, i0, i1, i2, v); }
 };
 
@@ -148,26 +164,27 @@ struct GlobalTabBF16 {
     return make_float4(bf16_to_float(p.x & 0xffffu), bf16_to_float(p.x >> 16), bf16_to_float(p.y & 0xffffu), 0.0f);
   }
   RC_HD float coul_at(int i0, int i1, int i2) const { return bf16_to_float(coul[((long)i0 * k1 + i1) * k2 + i2]); }
-  RC_HD void cool8(int i0, int i1, int i2, float4 (&v)[8]) const { corners8(*this, i0, i1, i2, v); }
+  RC_HD void cool8(int i0, int i1, int i2, float2 (&v)[8]) const { corners8se(*this, i0, i1, i2, v); }
   RC_HD void coul8(int i0, int i1, int i2, float (&v)[8]) const { corners8c(*this, i0, i1, i2, v); }
 };
 
 // The FP32 tables with a cell-blocked copy: the 8 corners of every table cell
-// stored together, corner (a, b, c) at a * 4 + b * 2 + c (cooling: 8 float4,
-// 128 bytes, one cache line; Coulomb: 8 floats, 32 bytes).  A corner gather
-// then touches one line instead of four, for 8 times the table memory.  The
+// stored together, corner (a, b, c) at a * 4 + b * 2 + c (cooling: 8 {brem,
+// se} pairs, 64 bytes, one aligned 64-byte block; Coulomb: 8 floats, 32
+// bytes).  A corner gather then touches one block instead of four pairs of
+// nodes, for 4 times the cooling and 8 times the Coulomb table memory.  The
 // node layout stays for the single-corner reads.
 struct CellTab {
   const float4* cool;
   const float* coul;
-  const float4* cool_cells;
+  const float2* cool_cells;
   const float* coul_cells;
   int c1, c2;
   int k1, k2;
   RC_HD float4 cool_at(int i0, int i1, int i2) const { return cool[((long)i0 * c1 + i1) * c2 + i2]; }
   RC_HD float coul_at(int i0, int i1, int i2) const { return coul[((long)i0 * k1 + i1) * k2 + i2]; }
-  RC_HD void cool8(int i0, int i1, int i2, float4 (&v)[8]) const {
-    const float4* p = cool_cells + (((long)i0 * (c1 - 1) + i1) * (c2 - 1) + i2) * 8;
+  RC_HD void cool8(int i0, int i1, int i2, float2 (&v)[8]) const {
+    const float2* p = cool_cells + (((long)i0 * (c1 - 1) + i1) * (c2 - 1) + i2) * 8;
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] = p[k];
   }
@@ -276,19 +293,19 @@ struct CellSolver {
     const double wN[2] = {1.0 - tN, tN};
     const double wB[2] = {1.0 - tB, tB};
     double lb = 0.0, lse = 0.0, hb = 0.0, hse = 0.0;
-    float4 v[8];
+    float2 v[8];
     tab.cool8(iN, i, iB, v);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         const double w = wN[a] * wB[b];
-        const float4 p = v[a * 4 + b];
-        const float4 q = v[a * 4 + 2 + b];
+        const float2 p = v[a * 4 + b];
+        const float2 q = v[a * 4 + 2 + b];
         lb += w * (double)p.x;
-        lse += w * ((double)p.y + (double)p.z);
+        lse += w * (double)p.y;
         hb += w * (double)q.x;
-        hse += w * ((double)q.y + (double)q.z);
+        hse += w * (double)q.y;
       }
     }
     const double fN = iN + tN, fB = iB + tB;
@@ -748,7 +765,7 @@ struct CellSolver {
     const double wT[2] = {1.0 - cT.t, cT.t};
     double y[3] = {0.0, 0.0, 0.0};
     float4 v[8];
-    tab.cool8(iN, cT.i, iB, v);
+    corners8(tab, iN, cT.i, iB, v);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll

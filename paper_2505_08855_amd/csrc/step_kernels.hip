@@ -375,7 +375,7 @@ extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n,
     st = ensure_cells(t, hs);
     if (st != RC_OK) return st;
     const rc_table_spec& sp = t->spec;
-    st = launch2(CellTab{(const float4*)t->d_cool, (const float*)t->d_coul, (const float4*)t->d_cool_cells,
+    st = launch2(CellTab{(const float4*)t->d_cool, (const float*)t->d_coul, (const float2*)t->d_cool_cells,
                          (const float*)t->d_coul_cells, sp.cool.n[1], sp.cool.n[2], sp.coul.n[1], sp.coul.n[2]});
     if (st != RC_OK) return st;
   } else if (two_pass) {
@@ -387,7 +387,7 @@ extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n,
     st = ensure_cells(t, hs);
     if (st != RC_OK) return st;
     const rc_table_spec& sp = t->spec;
-    st = launch(CellTab{(const float4*)t->d_cool, (const float*)t->d_coul, (const float4*)t->d_cool_cells,
+    st = launch(CellTab{(const float4*)t->d_cool, (const float*)t->d_coul, (const float2*)t->d_cool_cells,
                         (const float*)t->d_coul_cells, sp.cool.n[1], sp.cool.n[2], sp.coul.n[1], sp.coul.n[2]});
     if (st != RC_OK) return st;
   } else if (variant == RC_VARIANT_LDS) {

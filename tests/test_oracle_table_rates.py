@@ -114,8 +114,9 @@ MUTATIONS = (
     ("Q_brem = v_b / H", "q_brem = v_b / (H * H)", "q_brem = v_b / H"),
     ("Q_syn = v_s", "q_syn = v_s / H", "q_syn = v_s"),
     ("column N replaced by n_e", "uN = np.log10(n_e) + np.log10(H)", "uN = np.log10(n_e)"),
-    ("eta dropped from Q_thin", "q_thin = q_brem + v_eta * q_syn", "q_thin = q_brem + q_syn"),
-    ("eta dropped in q_rad_at", "q_thin = v_b / (H * H) + v_eta * v_s / H", "q_thin = v_b / (H * H) + v_s / H"),
+    ("eta dropped from Q_thin", "q_thin = q_brem + v_se / H", "q_thin = q_brem + q_syn"),
+    ("eta dropped from the se table", 'else self.t["synch"] + self.t["eta"])', 'else self.t["synch"])'),
+    ("Q_syn without 1/H in q_rad_at", "q_thin = v_b / (H * H) + v_se / H", "q_thin = v_b / (H * H) + v_se"),
     ("Coulomb sign flipped", '"q_cc": (T_i - T_e) * v_c', '"q_cc": (T_e - T_i) * v_c'),
     ("bridge tau_abs^2 term dropped", "1.5 * tau_abs * (tau_abs + tau_sca)", "1.5 * tau_abs * tau_sca"),
     ("sqrt3 term dropped", "1.0 + K.SQRT3 * tau_abs + 1.5", "1.0 + 1.5"),
