@@ -273,6 +273,29 @@ rc_status rc_tables_destroy(rc_tables t);
 rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n, double dt,
                        const rc_step_opts* opts, const rc_out* out, void* stream);
 
+/* Allocation-free variant of rc_cool_step, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation.  Same arguments, semantics and results as
+ * rc_cool_step (the same kernels), but it calls no hipMalloc, no hipFree and
+ * no allocating library routine (rc_cool_step allocates the two-pass step's
+ * scratch and the cell-blocked table copy on first use):
+ *  - the two-pass Newton step's scratch (resume records, classes, tile lists
+ *    and counts, about 59 bytes per cell) lives in a static device array
+ *    sized for RC_NOALLOC_MAX_CELLS cells (about 59 MiB), which every device
+ *    the library runs on holds until the process ends;
+ *  - n > RC_NOALLOC_MAX_CELLS returns RC_EINVAL before any launch;
+ *  - the cell-blocked table copy is read only if an earlier rc_cool_step or
+ *    rc_cool_step_batched on these tables built it: AUTO otherwise reads the
+ *    node layout (identical results), RC_VARIANT_CELL returns RC_ESTATE.
+ * The static scratch is shared by every call on a device and keeps the last
+ * call's contents; each call writes every scratch entry before reading it,
+ * so nothing has to start at zero.  Calls that overlap on one device (on
+ * different streams, or from threads without ordering) race on it and must
+ * be serialised by the caller. */
+#define RC_NOALLOC_MAX_CELLS (1 << 20)
+rc_status rc_cool_step_noalloc(rc_tables t, const rc_state* state, int64_t n, double dt,
+                               const rc_step_opts* opts, const rc_out* out, void* stream);
+
 /* One adaptive-mesh block of one accretion-rate state: cells first_cell ..
  * first_cell + n_cells - 1 of the state and output arrays, advanced with
  * dt_per_state[state_id]. */

@@ -8,6 +8,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "radcool.h"
 #include "rc_internal.hpp"
@@ -270,6 +271,54 @@ rc_status step_scratch(rc_tables_s* t, int64_t n, ResumeArgs* ra) {
   return RC_OK;
 }
 
+// ------------------------------------------------------------------ allocation-free step
+//
+// The two-pass step of rc_cool_step_noalloc takes its scratch from this
+// file-scope array instead of the table handle.  Sized for kNoAllocMaxCells
+// cells: resume records, classes, tile lists and tile counts, each part
+// 256-byte aligned, at offsets fixed for the maximum size.  In host code the
+// array's name is not a device address: kernels get the address that
+// hipGetSymbolAddress returns on each device (every device holds its own copy).
+constexpr int64_t kNoAllocMaxCells = RC_NOALLOC_MAX_CELLS;
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr int64_t kNoAllocTiles = (kNoAllocMaxCells + kTile - 1) / kTile;
+constexpr size_t kNaRec = 0;
+constexpr size_t kNaCls = kNaRec + align256(sizeof(NewtonResume) * (size_t)kNoAllocMaxCells);
+constexpr size_t kNaList = kNaCls + align256((size_t)kNoAllocMaxCells);
+constexpr size_t kNaCount = kNaList + align256(sizeof(uint16_t) * (size_t)kNoAllocTiles * kTile);
+constexpr size_t kNaBytes = kNaCount + align256(sizeof(unsigned) * (size_t)kNoAllocTiles);
+
+__device__ __align__(256) unsigned char scratch[kNaBytes];
+
+constexpr int kMaxDevices = 64;
+
+// the device address of `scratch` on device dev, looked up once per device
+// (with dev current) and kept for the life of the process
+rc_status noalloc_scratch(int dev, int64_t n, ResumeArgs* ra) {
+  static std::mutex mu;
+  static void* ptr[kMaxDevices] = {};
+  if (dev < 0 || dev >= kMaxDevices) return set_error(RC_EDEVICE, "rc_cool_step_noalloc: device index out of range");
+  void* p = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+      const hipError_t e = hipGetSymbolAddress(&ptr[dev], HIP_SYMBOL(scratch));
+      if (e != hipSuccess) {
+        ptr[dev] = nullptr;
+        return hip_fail(e, "rc_cool_step_noalloc: hipGetSymbolAddress(scratch)");
+      }
+    }
+    p = ptr[dev];
+  }
+  char* b = (char*)p;
+  ra->rec = (NewtonResume*)(b + kNaRec);
+  ra->cls = (uint8_t*)(b + kNaCls);
+  ra->list = (uint16_t*)(b + kNaList);
+  ra->count = (unsigned*)(b + kNaCount);
+  ra->ntiles = (n + kTile - 1) / kTile;
+  return RC_OK;
+}
+
 rc_status make_params(rc_tables t, double dt, const rc_step_opts* o, StepParams* P, bool host) {
   if (!o) return set_error(RC_EINVAL, "step options are NULL");
   if (o->scheme < RC_SCHEME_NEWTON || o->scheme > RC_SCHEME_RATES) return set_error(RC_EINVAL, "unknown scheme");
@@ -313,8 +362,14 @@ rc_status make_params(rc_tables t, double dt, const rc_step_opts* o, StepParams*
 
 using namespace rc;
 
-extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n, double dt,
-                                  const rc_step_opts* opts, const rc_out* out, void* stream) {
+namespace {
+
+// rc_cool_step, and with noalloc set rc_cool_step_noalloc: the two-pass
+// scratch comes from the static array and the cell-blocked table copy is used
+// only if it already exists (AUTO then falls back to the node layout, whose
+// results are identical; CELL without it is an error)
+rc_status cool_step_impl(rc_tables t, const rc_state* state, int64_t n, double dt, const rc_step_opts* opts,
+                         const rc_out* out, void* stream, bool noalloc) {
   if (!handle_ok(t)) return set_error(RC_ESTATE, "rc_cool_step: invalid table handle");
   if (!state || !out) return set_error(RC_EINVAL, "rc_cool_step: state or out is NULL");
   if (n < 0) return set_error(RC_EINVAL, "rc_cool_step: n < 0");
@@ -328,6 +383,17 @@ extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n,
   // bfloat16 tables
   int variant = opts->variant != RC_VARIANT_AUTO ? opts->variant
               : t->spec.value_dtype == RC_VALUE_F32 ? RC_VARIANT_CELL : RC_VARIANT_GLOBAL;
+  if (noalloc) {
+    if (n > kNoAllocMaxCells)
+      return set_error(RC_EINVAL, "rc_cool_step_noalloc: n exceeds RC_NOALLOC_MAX_CELLS (the static scratch)");
+    const bool have_cells = t->d_cool_cells && t->d_coul_cells;
+    if (variant == RC_VARIANT_CELL && !have_cells) {
+      if (opts->variant == RC_VARIANT_CELL)
+        return set_error(RC_ESTATE, "rc_cool_step_noalloc: the cell-blocked table copy does not exist yet (it is "
+                                    "built by the first rc_cool_step that reads it)");
+      variant = RC_VARIANT_GLOBAL;
+    }
+  }
   if (variant == RC_VARIANT_DIRECT && opts->scheme != RC_SCHEME_RATES)
     return set_error(RC_EUNSUPPORTED, "rc_cool_step: the DIRECT variant evaluates rates only (scheme RC_SCHEME_RATES)");
   if (variant == RC_VARIANT_TEX)
@@ -363,7 +429,7 @@ extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n,
   const auto launch2 = [&](auto tab) -> rc_status {
       using Tab = decltype(tab);
       ResumeArgs ra;
-      rc_status rs = step_scratch(t, n, &ra);
+      rc_status rs = noalloc ? noalloc_scratch(dev, n, &ra) : step_scratch(t, n, &ra);
       if (rs != RC_OK) return rs;
       hipLaunchKernelGGL((k_newton_first<Tab>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, s, o, ra, n);
       hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)ra.ntiles), dim3(256), 0, hs, ra, n);
@@ -372,7 +438,7 @@ extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n,
       return RC_OK;
   };
   if (two_pass && variant == RC_VARIANT_CELL) {
-    st = ensure_cells(t, hs);
+    st = noalloc ? RC_OK : ensure_cells(t, hs);
     if (st != RC_OK) return st;
     const rc_table_spec& sp = t->spec;
     st = launch2(CellTab{(const float4*)t->d_cool, (const float*)t->d_coul, (const float2*)t->d_cool_cells,
@@ -384,7 +450,7 @@ extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n,
   } else if (variant == RC_VARIANT_DIRECT) {
     hipLaunchKernelGGL(k_direct, dim3((unsigned)grid), dim3(block), 0, hs, P, s, o, n);
   } else if (variant == RC_VARIANT_CELL) {
-    st = ensure_cells(t, hs);
+    st = noalloc ? RC_OK : ensure_cells(t, hs);
     if (st != RC_OK) return st;
     const rc_table_spec& sp = t->spec;
     st = launch(CellTab{(const float4*)t->d_cool, (const float*)t->d_coul, (const float2*)t->d_cool_cells,
@@ -412,4 +478,16 @@ extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n,
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "rc_cool_step launch");
   return RC_OK;
+}
+
+}  // namespace
+
+extern "C" rc_status rc_cool_step(rc_tables t, const rc_state* state, int64_t n, double dt,
+                                  const rc_step_opts* opts, const rc_out* out, void* stream) {
+  return cool_step_impl(t, state, n, dt, opts, out, stream, false);
+}
+
+extern "C" rc_status rc_cool_step_noalloc(rc_tables t, const rc_state* state, int64_t n, double dt,
+                                          const rc_step_opts* opts, const rc_out* out, void* stream) {
+  return cool_step_impl(t, state, n, dt, opts, out, stream, true);
 }

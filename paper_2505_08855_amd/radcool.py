@@ -26,7 +26,7 @@ SCHEMES = {"newton": 0, "explicit16": 1, "rates": 2}
 
 EXPORTED = ("rc_default_spec", "rc_default_opts", "rc_build_tables", "rc_tables_import",
             "rc_tables_export", "rc_tables_info", "rc_tables_save", "rc_tables_load",
-            "rc_tables_destroy", "rc_cool_step", "rc_constants", "rc_selftest_node_host",
+            "rc_tables_destroy", "rc_cool_step", "rc_cool_step_noalloc", "rc_constants", "rc_selftest_node_host",
             "rc_selftest_special_host", "rc_selftest_step_host", "rc_last_error",
             "rc_cool_step_backward", "rc_selftest_backward_host", "rc_cool_step_batched",
             "rc_plan_create", "rc_plan_launch", "rc_plan_info", "rc_plan_destroy",
@@ -35,6 +35,7 @@ EXPORTED = ("rc_default_spec", "rc_default_opts", "rc_build_tables", "rc_tables_
             "rc_rates4d", "rc_selftest_node4d_host", "rc_selftest_rates4d_host", "rc_apply_cooling",
             "rc_selftest_coupling_host", "rc_batched_workgroup_items", "rc_plan_workgroup_items")
 MAX_STATES = 64
+NOALLOC_MAX_CELLS = 1 << 20      # RC_NOALLOC_MAX_CELLS
 
 
 class RadcoolError(RuntimeError):
@@ -137,6 +138,7 @@ def lib():
             "rc_tables_load": (i32, [ctypes.c_char_p, vp, P(vp)]),
             "rc_tables_destroy": (i32, [vp]),
             "rc_cool_step": (i32, [vp, P(State), i64, dbl, P(StepOpts), P(Out), vp]),
+            "rc_cool_step_noalloc": (i32, [vp, P(State), i64, dbl, P(StepOpts), P(Out), vp]),
             "rc_constants": (i32, [vp, i32]),
             "rc_selftest_node_host": (i32, [P(TableSpec), i32, i32, i32, i32, P(dbl)]),
             "rc_selftest_special_host": (i32, [i32, vp, vp, i64]),
@@ -364,6 +366,21 @@ def cool_step(tables, state, dt, opts=None, out=None, diagnostics=False, stream=
               for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc", "status", "Q_brem", "Q_syn", "eta")])
     check(lib().rc_cool_step(tables.handle, ctypes.byref(st), n, float(dt), ctypes.byref(opts),
                              ctypes.byref(o), _stream_ptr(stream)))
+    return out
+
+
+def cool_step_noalloc(tables, state, dt, out, opts=None, stream=None):
+    """rc_cool_step_noalloc: the step of cool_step with no device allocation in
+    the library (static scratch, at most NOALLOC_MAX_CELLS cells).  ``out``
+    supplies every output tensor (T_e_new, T_i_new, Q_rad, Q_cc, status;
+    optionally Q_brem, Q_syn, eta).  Returns ``out``."""
+    n = _check_state(state)
+    opts = opts or default_opts()
+    _check_out(out, n, opts)
+    st = _state(state)
+    o = _out_struct(out)
+    check(lib().rc_cool_step_noalloc(tables.handle, ctypes.byref(st), n, float(dt), ctypes.byref(opts),
+                                     ctypes.byref(o), _stream_ptr(stream)))
     return out
 
 
