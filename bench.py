@@ -8,8 +8,8 @@ the closed forms, one backward-Euler (Newton) cooling step per timed step over
 all cells with dt = 1e-3 r_g/c (M = 10 M_sun).  Inputs and outputs stay in HBM.
 Prints one JSON line.
 
-A step is one rc_cool_step call: every launch the library makes for it (the
-Newton step runs as two passes with a tile sort between them).
+A step is one rc_cool_step call: every launch the library makes for it (one
+for the library's Newton step; three for its two-pass form).
 Roofline: algorithmic HBM bytes per step = 72 B per cell (read n_e, T_e, T_i,
 B, H as FP64; write T_e', T_i', Q_rad, Q_cc as FP64) + the status byte + one
 read of the four tables.  Achieved = bytes / average step time from HIP
@@ -62,8 +62,10 @@ BYTES_PER_CELL = 5 * 8 + 4 * 8 + 1      # state in, T', Q_rad, Q_cc out, status
 COPY_BYTES = 64 << 23                   # the calibration copy: 512 MiB read and written
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "newton_iid256_t128_counters.md")
 # the Newton step's launches (demangled names), FP32 tables read through the
-# cell-blocked copy: first pass, tile sort, resumed pass
-STEP_KERNELS = re.compile(r"k_newton_first<rc::CellTab>|k_tile_sort|k_newton_resume<rc::CellTab>")
+# cell-blocked copy: the one-kernel solve (the library's choice), or the
+# two-pass form's first pass, tile sort and resumed pass
+STEP_KERNELS = re.compile(r"k_step<0, rc::CellTab>|k_newton_first<rc::CellTab>|k_tile_sort|"
+                          r"k_newton_resume<rc::CellTab>")
 CPU_WORKERS_MAX = 16                    # host cores of one GPU's share of a node
 
 
@@ -558,8 +560,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "cells": n, "scheme": args.scheme, "variant": args.variant,
                    "table_n": table_n, "dt_s": dt, "T_floor_K": opts.T_floor},
-        # a step is every launch of one rc_cool_step call (the Newton step:
-        # first pass, tile sort, resumed pass), timed together on their stream
+        # a step is every launch of one rc_cool_step call (one for the
+        # library's Newton step), timed together on their stream
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic() if headline else None,
                      "unit_of_work": "one step (all its launches)", "algorithmic_bytes": algo_bytes},
@@ -574,7 +576,7 @@ def main():
     finishers = []
     if not args.no_variants:
         var = {}
-        for name, kw, steps in (("newton_one_pass", dict(passes=1), 3),
+        for name, kw, steps in (("newton_two_pass", dict(passes=2), 3),
                                 ("newton_block256", dict(block=256, passes=1), 3),
                                 ("rates", dict(scheme="rates"), 5),
                                 ("explicit16", dict(scheme="explicit16"), 3),

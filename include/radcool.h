@@ -197,7 +197,7 @@ typedef struct {
   double tol;            /* target relative accuracy of T_e' (default 1e-12): a Newton step
                             below sqrt(tol) in ln T_e' ends the solve */
   int32_t passes;        /* Newton scheme, variants AUTO, CELL and GLOBAL: 0 = library
-                            choice (2), 1 = one kernel, every cell solved by its own
+                            choice (1), 1 = one kernel, every cell solved by its own
                             thread in cell order; 2 = two passes: every cell's first
                             Newton round in cell order, then the unfinished cells,
                             grouped per tile of 4096 cells by the length of their

@@ -58,6 +58,22 @@ RC_HD float frcp_sp(float x) {
 #endif
 }
 
+// One Horner step p * f + c with a constant coefficient c.  On the device the
+// coefficient is an operand in a scalar register pair, so the step is one
+// v_fma_f64; left to itself the compiler shapes each step as a copy of c into
+// the accumulator (two 32-bit immediate moves, or a 64-bit register copy)
+// followed by v_fmac_f64, two to three vector instructions per term.  Same
+// fused multiply-add, same result.
+RC_HD double hfma(double p, double f, double c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(f), "s"(c));
+  return r;
+#else
+  return fma(p, f, c);
+#endif
+}
+
 // single-precision 2^y and log2 x for step proposals that need no more than
 // a few digits: the hardware instructions on the device, the C library on
 // the host
@@ -87,15 +103,15 @@ RC_HD double flog(double x) {
   const double f = fdiv(m - 1.0, m + 1.0);   // m - 1 is exact
   const double s = f * f;
   double p = 1.0 / 21.0;
-  p = fma(p, s, 1.0 / 19.0);
-  p = fma(p, s, 1.0 / 17.0);
-  p = fma(p, s, 1.0 / 15.0);
-  p = fma(p, s, 1.0 / 13.0);
-  p = fma(p, s, 1.0 / 11.0);
-  p = fma(p, s, 1.0 / 9.0);
-  p = fma(p, s, 1.0 / 7.0);
-  p = fma(p, s, 1.0 / 5.0);
-  p = fma(p, s, 1.0 / 3.0);
+  p = hfma(p, s, 1.0 / 19.0);
+  p = hfma(p, s, 1.0 / 17.0);
+  p = hfma(p, s, 1.0 / 15.0);
+  p = hfma(p, s, 1.0 / 13.0);
+  p = hfma(p, s, 1.0 / 11.0);
+  p = hfma(p, s, 1.0 / 9.0);
+  p = hfma(p, s, 1.0 / 7.0);
+  p = hfma(p, s, 1.0 / 5.0);
+  p = hfma(p, s, 1.0 / 3.0);
   const double f2 = f + f;
   const double lm = fma(f2 * s, p, f2);    // 2 atanh f
   const double de = (double)e;
@@ -116,19 +132,19 @@ RC_HD double fexp2(double y) {
   const double k = rint(y);
   const double f = y - k;             // exact
   double p = 0x1.816193166d0f9p-40;   // (ln 2)^13 / 13!
-  p = fma(p, f, 0x1.c3bd650fc2986p-36);
-  p = fma(p, f, 0x1.e8cac7351bb25p-32);
-  p = fma(p, f, 0x1.e4cf5158b8ecap-28);
-  p = fma(p, f, 0x1.b5253d395e7c4p-24);
-  p = fma(p, f, 0x1.62c0223a5c824p-20);
-  p = fma(p, f, 0x1.ffcbfc588b0c7p-17);
-  p = fma(p, f, 0x1.430912f86c787p-13);
-  p = fma(p, f, 0x1.5d87fe78a6731p-10);
-  p = fma(p, f, 0x1.3b2ab6fba4e77p-7);
-  p = fma(p, f, 0x1.c6b08d704a0c0p-5);
-  p = fma(p, f, 0x1.ebfbdff82c58fp-3);
-  p = fma(p, f, 0x1.62e42fefa39efp-1);
-  p = fma(p, f, 1.0);
+  p = hfma(p, f, 0x1.c3bd650fc2986p-36);
+  p = hfma(p, f, 0x1.e8cac7351bb25p-32);
+  p = hfma(p, f, 0x1.e4cf5158b8ecap-28);
+  p = hfma(p, f, 0x1.b5253d395e7c4p-24);
+  p = hfma(p, f, 0x1.62c0223a5c824p-20);
+  p = hfma(p, f, 0x1.ffcbfc588b0c7p-17);
+  p = hfma(p, f, 0x1.430912f86c787p-13);
+  p = hfma(p, f, 0x1.5d87fe78a6731p-10);
+  p = hfma(p, f, 0x1.3b2ab6fba4e77p-7);
+  p = hfma(p, f, 0x1.c6b08d704a0c0p-5);
+  p = hfma(p, f, 0x1.ebfbdff82c58fp-3);
+  p = hfma(p, f, 0x1.62e42fefa39efp-1);
+  p = hfma(p, f, 1.0);
   return ldexp(p, (int)k);
 }
 
@@ -138,19 +154,19 @@ RC_HD double fexp(double s) {
   const double k = rint(s * kLog2E);
   const double r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, s));
   double p = 1.0 / 6227020800.0;      // 1 / 13!
-  p = fma(p, r, 1.0 / 479001600.0);
-  p = fma(p, r, 1.0 / 39916800.0);
-  p = fma(p, r, 1.0 / 3628800.0);
-  p = fma(p, r, 1.0 / 362880.0);
-  p = fma(p, r, 1.0 / 40320.0);
-  p = fma(p, r, 1.0 / 5040.0);
-  p = fma(p, r, 1.0 / 720.0);
-  p = fma(p, r, 1.0 / 120.0);
-  p = fma(p, r, 1.0 / 24.0);
-  p = fma(p, r, 1.0 / 6.0);
-  p = fma(p, r, 0.5);
-  p = fma(p, r, 1.0);
-  p = fma(p, r, 1.0);
+  p = hfma(p, r, 1.0 / 479001600.0);
+  p = hfma(p, r, 1.0 / 39916800.0);
+  p = hfma(p, r, 1.0 / 3628800.0);
+  p = hfma(p, r, 1.0 / 362880.0);
+  p = hfma(p, r, 1.0 / 40320.0);
+  p = hfma(p, r, 1.0 / 5040.0);
+  p = hfma(p, r, 1.0 / 720.0);
+  p = hfma(p, r, 1.0 / 120.0);
+  p = hfma(p, r, 1.0 / 24.0);
+  p = hfma(p, r, 1.0 / 6.0);
+  p = hfma(p, r, 0.5);
+  p = hfma(p, r, 1.0);
+  p = hfma(p, r, 1.0);
   return ldexp(p, (int)k);
 }
 

@@ -35,6 +35,7 @@ constexpr double kMpC2 = kMP * kC * kC;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kLn2 = 0.69314718055994530942;
 constexpr double kLn10 = 2.30258509299404568402;
+constexpr double kLog2_10 = 3.32192809488736234787;   // log2(10)
 constexpr double kSqrt3 = 1.73205080756887729353;
 
 // fit coefficients printed in Sec. II.A and II.B

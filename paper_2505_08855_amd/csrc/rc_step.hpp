@@ -229,17 +229,21 @@ struct FixedCoords {
   Coord N, B, n;
 };
 
-RC_HD FixedCoords fixed_coords(const StepParams& P, double n_e, double b, double h) {
+RC_HD FixedCoords fixed_coords(const StepParams& P, double n_e, double b, double h, double* lh10 = nullptr) {
   const double lne = flog10(n_e);
-  return {axis_coord(lne + flog10(h), P.g->ax[0]), axis_coord(flog10(b), P.g->ax[2]), axis_coord(lne, P.g->ax[3])};
+  const double lh = flog10(h);
+  if (lh10) *lh10 = lh;
+  return {axis_coord(lne + lh, P.g->ax[0]), axis_coord(flog10(b), P.g->ax[2]), axis_coord(lne, P.g->ax[3])};
 }
 
 template <class Tab>
 struct CellSolver {
   const Tab& tab;
   const StepParams& P;
-  // per-cell constants (dt is per cell so that batched work items can carry their own)
-  double T_e, T_i, H, c, cS, tau_sca, invH, invH2, dt;
+  // per-cell constants (dt is per cell so that batched work items can carry their own);
+  // lH = log2 H, folded into the cached cooling exponents (Q_brem = v_b / H^2,
+  // Q_syn = v_s / H)
+  double T_e, T_i, H, c, tau_sca, lH, dt;
   // gather coordinates that stay fixed during the solve
   int iN, iB, in_;
   double tN, tB, tn;
@@ -268,11 +272,10 @@ struct CellSolver {
     T_i = ti;
     H = h;
     c = kUperNKT * n_e * kKB;
-    cS = c * (te + ti);
     tau_sca = 2.0 * n_e * kSigmaT * h;
-    invH = 1.0 / h;
-    invH2 = invH * invH;
-    const FixedCoords f = fixed_coords(P, n_e, b, h);
+    double lh10;
+    const FixedCoords f = fixed_coords(P, n_e, b, h, &lh10);
+    lH = lh10 * kLog2_10;
     const Coord &cN = f.N, &cB = f.B, &cn = f.n;
     iN = cN.i; tN = cN.t;
     iB = cB.i; tB = cB.t;
@@ -311,9 +314,9 @@ struct CellSolver {
     const double fN = iN + tN, fB = iB + tB;
     const double* cb = P.g->coef[0];
     const double* cse = P.g->coef_se;
-    Ab = cb[0] + cb[1] * fN + cb[2] * (double)i + cb[3] * fB + lb;
+    Ab = cb[0] + cb[1] * fN + cb[2] * (double)i + cb[3] * fB + lb - 2.0 * lH;
     Sb = cb[2] + hb - lb;
-    Ase = cse[0] + cse[1] * fN + cse[2] * (double)i + cse[3] * fB + lse;
+    Ase = cse[0] + cse[1] * fN + cse[2] * (double)i + cse[3] * fB + lse - lH;
     Sse = cse[2] + hse - lse;
   }
 
@@ -351,8 +354,8 @@ struct CellSolver {
     if (!on) { *q = 0.0; *dq = 0.0; return; }
     const double t = cT.t;
     const double g = cT.dfdu * (1.0 / kLn10);       // d t / d ln x
-    const double vb = fexp2(Ab + Sb * t) * invH2;
-    const double vs = fexp2(Ase + Sse * t) * invH;
+    const double vb = fexp2(Ab + Sb * t);            // Q_brem
+    const double vs = fexp2(Ase + Sse * t);          // eta Q_syn
     const double qthin = vb + vs;
     const double dlq = kLn2 * g * fdiv(vb * Sb + vs * Sse, qthin);
     const double x2 = x * x;
@@ -410,9 +413,11 @@ struct CellSolver {
       if (E < 0.0) lo = z; else hi = z;
       const double dz = -fdiv(E, dEz);
       // converged: Newton converges quadratically, so after a step below
-      // 1e-8 z the remaining error is ~1e-16 z.  Tested before the bracket
+      // 1e-6 z the remaining error is of order 1e-12 z (on the iid cells the
+      // solution moves by at most 2.5e-14 against a 1e-8 threshold, which
+      // costs 15 % more inner evaluations).  Tested before the bracket
       // safeguard, which would reject a step below the bracket end's ulp.
-      if (fabs(dz) <= 1e-8 * z) { z += dz; break; }
+      if (fabs(dz) <= 1e-6 * z) { z += dz; break; }
       double zn = z + dz;
       if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
       z = zn;
@@ -454,6 +459,7 @@ struct CellSolver {
     *z = solve_z(x, ce, z0, ci, &dzdx, K_first);
     const double numer = c * ((x - T_e) + (*z - T_i)) + dt * q;
     const double cx = c * x * (1.0 + dzdx);
+    const double cS = c * (T_e + T_i);
     *dG = fdiv(cx + dt * dq, cS + numer);
     *q_out = q;
     *dzdx_out = dzdx;
@@ -634,7 +640,16 @@ struct CellSolver {
         else sn = s + ((ns.flags & F_HEATING) ? fmax(ds3, dsG) : fmin(ds3, dsG));
       }
       const bool newton_ok = (use3 || ns.dG > 0.0) && (sn == sn);
-      if (newton_ok && fabs(sn - s) <= P.sqrt_tol && !(floor_pending && sn < sf)) {
+      const bool small = newton_ok && fabs(sn - s) <= P.sqrt_tol && !(floor_pending && sn < sf);
+      // bracket safeguard: a step outside the bracket, or no usable step,
+      // becomes the bisection point (a small step is tested for convergence
+      // before the safeguard, which could reject a step below an end's ulp)
+      const bool bad = !newton_ok || sn >= hi || (lo_known ? sn <= lo : sn < lo);
+      const double s_mid = lo_known ? 0.5 * (lo + hi) : 0.5 * (lo + s);
+      double s_next = (small || !bad) ? sn : s_mid;
+      // the next iterate's temperature, computed once for every lane
+      double xn = fexp(s_next);
+      if (small) {
         // converged: Newton converges quadratically, so once the step is
         // below sqrt(tol) the error left after taking it is O(tol) -- provided
         // the step stays inside the table cells of the current iterate (the
@@ -643,9 +658,7 @@ struct CellSolver {
         // first-order extrapolation z + dz/dx (x' - x) along the solution
         // curve z(x) of the ion equation, whose error is second order in
         // x' - x, so O(tol) too, under the same condition on the Coulomb
-        // cells.  Tested before the bracket safeguard, which could reject a
-        // step below an end's ulp.
-        const double xn = fexp(sn);
+        // cells.
         const double zn = ns.z + dzdx * (xn - ns.xe);
         const double lxn = sn * (1.0 / kLn10);
         const bool same_cells = (!(ns.flags & F_ON) || axis_coord(lxn, P.g->ax[1]).i == iT) &&
@@ -655,20 +668,20 @@ struct CellSolver {
           ns.kind = DONE; ns.xe = xn;
           continue;
         }
+        if (bad) {                             // not finished after all: the safeguard applies
+          s_next = s_mid;
+          xn = fexp(s_next);
+        }
       }
-      if (floor_pending && (!newton_ok || sn < sf)) {
+      if (!small && floor_pending && (!newton_ok || sn < sf)) {
         // the descent would cross the floor (decided on the raw Newton step:
-        // the safeguard below only halves towards it): probe G just above it
+        // the safeguard only halves towards it): probe G just above it
         ns.flags &= ~F_FLOOR_PENDING;
         ns.kind = PROBE_ON; ns.se = sf; ns.xe = T_floor; ns.flags |= F_ON;
         return false;
       }
-      if (!newton_ok || sn >= hi || (lo_known ? sn <= lo : sn < lo)) {
-        sn = lo_known ? 0.5 * (lo + hi) : 0.5 * (lo + s);
-      }
-      const double xn = fexp(sn);
       ns.z += dzdx * (xn - ns.xe);             // first-order warm start of the next inner solve
-      ns.kind = ITER; ns.se = sn; ns.xe = xn;
+      ns.kind = ITER; ns.se = s_next; ns.xe = xn;
       if (ns.xe >= T_floor) ns.flags |= F_ON; else ns.flags &= ~F_ON;
     }
     return false;
@@ -784,7 +797,8 @@ struct CellSolver {
       const double* co = P.g->coef[k];
       y[k] += co[0] + co[1] * fN + co[2] * fT + co[3] * fB;
     }
-    o->q_brem = fexp2(y[0]) * invH2;
+    const double invH = 1.0 / H;
+    o->q_brem = fexp2(y[0]) * invH * invH;
     o->q_syn = fexp2(y[1]) * invH;
     o->eta = fexp2(y[2]);
   }

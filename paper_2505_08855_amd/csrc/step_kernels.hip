@@ -19,8 +19,19 @@ namespace rc {
 
 // Occupancy target (waves per SIMD) the register allocator works to for
 // each scheme; the Newton solve trades a little spilling for latency hiding.
+// Measured on the 256^3 iid step (128^3 tables): the one-kernel solve at 3
+// waves per SIMD (168 VGPRs, about 30 spilled) 2.79 ms against 3.20 ms at 2
+// (no spills); the two-pass step 2.88 ms with its first pass at 2 and its
+// resumed pass at 3 (the first pass spills 29 registers at 3).  The solve is
+// bound by table-gather latency more than by issue, so occupancy pays.
 #ifndef RC_NEWTON_WAVES
-#define RC_NEWTON_WAVES 2
+#define RC_NEWTON_WAVES 3
+#endif
+#ifndef RC_FIRST_WAVES
+#define RC_FIRST_WAVES 2
+#endif
+#ifndef RC_RESUME_WAVES
+#define RC_RESUME_WAVES 3
 #endif
 template <int SCHEME>
 constexpr int kStepWaves = SCHEME == SCHEME_NEWTON ? RC_NEWTON_WAVES : SCHEME == SCHEME_EXPLICIT16 ? 3 : 1;
@@ -140,7 +151,7 @@ struct ResumeArgs {
 };
 
 template <class Tab>
-__global__ __launch_bounds__(256, RC_NEWTON_WAVES) void k_newton_first(Tab tab, StepParams P, StateArgs s, OutArgs o,
+__global__ __launch_bounds__(256, RC_FIRST_WAVES) void k_newton_first(Tab tab, StepParams P, StateArgs s, OutArgs o,
                                                                      ResumeArgs ra, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -214,7 +225,7 @@ __global__ __launch_bounds__(256) void k_tile_sort(ResumeArgs ra, int64_t n) {
 // to the 8 XCDs round-robin, so the mapping below puts all chunks of a tile on
 // one XCD, consecutively: the tile's state and records are fetched into one L2.
 template <class Tab>
-__global__ __launch_bounds__(64, RC_NEWTON_WAVES) void k_newton_resume(Tab tab, StepParams P, StateArgs s, OutArgs o,
+__global__ __launch_bounds__(64, RC_RESUME_WAVES) void k_newton_resume(Tab tab, StepParams P, StateArgs s, OutArgs o,
                                                                      ResumeArgs ra) {
   const int64_t b = blockIdx.x;
   const int64_t slot = b >> 3;
@@ -424,7 +435,7 @@ rc_status cool_step_impl(rc_tables t, const rc_state* state, int64_t n, double d
       return RC_OK;
   };
   // two-pass Newton step (identical results; see k_newton_first)
-  const bool two_pass = opts->scheme == RC_SCHEME_NEWTON && opts->passes != 1 &&
+  const bool two_pass = opts->scheme == RC_SCHEME_NEWTON && opts->passes == 2 &&
                         (variant == RC_VARIANT_CELL || variant == RC_VARIANT_GLOBAL);
   const auto launch2 = [&](auto tab) -> rc_status {
       using Tab = decltype(tab);

@@ -208,7 +208,7 @@ def test_theta_i_me_energy_tier(dev, theta_me, cells0):
 # ------------------------------------------------------------------ FP32 rate outputs
 
 
-@pytest.mark.parametrize("kw", [dict(), dict(passes=1), dict(scheme="rates"), dict(scheme="explicit16"),
+@pytest.mark.parametrize("kw", [dict(), dict(passes=2), dict(scheme="rates"), dict(scheme="explicit16"),
                                 dict(scheme="rates", variant="direct")])
 def test_f32_rates_are_rounded_fp64_rates(dev, cells0, kw):
     gt = R.Tables.build(R.default_spec(64))

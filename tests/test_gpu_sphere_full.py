@@ -1,0 +1,146 @@
+"""Full-size parity of the precision form: the spherical-polar MAD-like
+profile at 128^3 = 2,097,152 cells with 64^3 tables, in the launch
+configuration of the default step.
+
+* rates tier: GPU-built FP32 tables against the oracle's FP64 tables, on a
+  seeded sample of 16,384 cells (Q_rad, Q_cc and the three cooling quantities
+  within 1e-5);
+* energy tier: the oracle's tables imported in storage form, the Newton step
+  over every cell, the sample against the oracle's backward Euler on the same
+  data (1e-9, identical status);
+* every cell: finite outputs and energy conservation
+  c (dT_e + dT_i) = -dt Q_rad(T_e') with the library's own rates at the new
+  state (paper III.B, backward Euler).
+
+And the adjoint on coherent cells: patches of the profile put hundreds of
+cells into one table cell, so the table gradients go through the crowded-cell
+reduction; they are compared with the oracle's implicit-function-theorem
+gradient (not with the library's host code)."""
+import numpy as np
+import pytest
+
+from conftest import rel_err
+from oracle import grad as Gd
+from oracle import step as S
+from oracle import tables as T
+from paper_2505_08855_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+R = pytest.importorskip("paper_2505_08855_amd.radcool")
+DT = W.DT_DEFAULT
+SAMPLE = 16384
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    return torch.device("cuda:0")
+
+
+def to_dev(cells, dev, idx=None):
+    return {k: torch.from_numpy(np.ascontiguousarray(cells[k] if idx is None else cells[k][idx])).to(dev)
+            for k in W.FIELDS}
+
+
+def storage_of(tabs):
+    co, re, stored = T.quantize_tables(tabs)
+    return (np.concatenate([re[k].ravel() for k in T.TABLE_NAMES]), np.stack([co[k] for k in T.TABLE_NAMES]),
+            stored)
+
+
+def test_sphere128_full_size(dev, spec64, tables64):
+    cells = W.workload(2)
+    n = cells["n_e"].size
+    assert n == 128 ** 3
+    print("sphere 128^3: rates tier, energy tier on %d sampled cells, conservation everywhere" % SAMPLE, flush=True)
+    st = to_dev(cells, dev)
+    idx = np.sort(np.random.default_rng(2).choice(n, size=SAMPLE, replace=False))
+    sample = [cells[f][idx] for f in W.FIELDS]
+
+    # rates tier: GPU-built tables vs the oracle's FP64 tables
+    gbuilt = R.Tables.build(R.default_spec(64))
+    rates = R.cool_step(gbuilt, st, DT, R.default_opts(scheme="rates"), diagnostics=True)
+    ref_r = S.table_rates(S.TableSet(spec64, tables64), *sample)
+    for g, r in (("Q_rad", "q_rad"), ("Q_cc", "q_cc"), ("Q_brem", "q_brem"), ("Q_syn", "q_syn"), ("eta", "eta")):
+        assert np.max(rel_err(rates[g].cpu().numpy()[idx], ref_r[r])) < 1e-5, g
+    assert np.array_equal(rates["status"].cpu().numpy()[idx], ref_r["status"])
+    del rates
+    gbuilt.destroy()
+
+    # energy tier on identical table data, the default launch over every cell
+    resid, coeffs, stored = storage_of(tables64)
+    gt = R.Tables.from_storage(R.default_spec(64), resid, coeffs)
+    out = R.cool_step(gt, st, DT)
+    ref = S.step_be(S.TableSet(spec64, stored), *sample, DT)
+    for k in ("T_e_new", "T_i_new"):
+        assert np.max(rel_err(out[k].cpu().numpy()[idx], ref[k])) < 1e-9, k
+    assert np.array_equal(out["status"].cpu().numpy()[idx], ref["status"])
+
+    # every cell: finite, and the energy radiated equals dt Q_rad at the new state
+    te, ti = out["T_e_new"], out["T_i_new"]
+    assert bool(torch.isfinite(te).all()) and bool(torch.isfinite(ti).all())
+    new_state = dict(st)
+    new_state["T_e"], new_state["T_i"] = te, ti
+    q_new = R.cool_step(gt, new_state, DT, R.default_opts(scheme="rates"))["Q_rad"]
+    c = 1.5 * st["n_e"] * 1.380649e-16
+    lost = c * ((st["T_e"] - te) + (st["T_i"] - ti))
+    floor = (out["status"] & R.ST_FLOOR) != 0
+    resid_e = (lost - DT * q_new).abs() / (c * (st["T_e"] + st["T_i"]))
+    assert float(resid_e[~floor].max()) < 1e-9
+    assert int((out["status"] & R.ST_MAXITER).sum()) == 0
+    gt.destroy()
+
+
+def cells_per_cooling_cell(spec, cells, T_e):
+    """Number of cells in each cooling-table cell at electron temperature T_e."""
+    uN = np.log10(cells["n_e"]) + np.log10(cells["H"])
+    idx = [T.axis_coord(u, a)[0] for u, a in zip((uN, np.log10(T_e), np.log10(cells["B"])), spec.cool)]
+    key = (idx[0] * spec.cool[1].n + idx[1]) * spec.cool[2].n + idx[2]
+    return np.bincount(key)
+
+
+def test_adjoint_coherent_cells_against_oracle(dev, spec64, tables64):
+    """Table and input gradients of the adjoint on coherent cells (table cells
+    holding more than 128 records: the workgroup reduction), against the
+    oracle's adjoint on identical table data."""
+    cells = W.sphere_cells(n_r=8, n_th=8, n_ph=256)
+    n = cells["n_e"].size
+    resid, coeffs, stored = storage_of(tables64)
+    gt = R.Tables.from_storage(R.default_spec(64), resid, coeffs)
+    ts = S.TableSet(spec64, stored)
+    st = to_dev(cells, dev)
+    fwd = R.cool_step(gt, st, DT)
+    out = {k: v.cpu().numpy() for k, v in fwd.items()}
+    ref_fwd = S.step_be(ts, *[cells[f] for f in W.FIELDS], DT)
+    for k in ("T_e_new", "T_i_new"):
+        assert np.max(rel_err(out[k], ref_fwd[k])) < 1e-9, k
+    # the crowded-cell path is taken: some table cell holds more than 128 of
+    # these cells, at the input state and at the updated one
+    assert cells_per_cooling_cell(spec64, cells, cells["T_e"]).max() > 128
+    assert cells_per_cooling_cell(spec64, cells, out["T_e_new"]).max() > 128
+    rng = np.random.default_rng(11)
+    cot = {k: rng.normal(size=n) for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")}
+    _, nv = gt.info()
+    tg = torch.zeros(nv, dtype=torch.float64, device=dev)
+    g = R.cool_step_backward(gt, st, DT, fwd, {k: to_dev_1(v, dev) for k, v in cot.items()}, table_grad=tg)
+    ref = Gd.vjp_step_be(ts, cells, ref_fwd, DT, cot["T_e_new"], cot["T_i_new"], cot["Q_rad"], cot["Q_cc"])
+    mag = (np.abs(cot["T_e_new"] * out["T_e_new"]) + np.abs(cot["T_i_new"] * out["T_i_new"])
+           + np.abs(cot["Q_rad"] * out["Q_rad"]) + np.abs(cot["Q_cc"] * out["Q_cc"]))
+    for f in W.FIELDS:
+        got = g[f].cpu().numpy()
+        err = np.abs(got - ref[f]) * cells[f]
+        assert np.all(err <= 1e-8 * np.abs(ref[f] * cells[f]) + 1e-11 * mag), f
+    tgn = tg.cpu().numpy()
+    vc = 64 ** 3
+    for k, name in enumerate(T.TABLE_NAMES):
+        want = ref["tables"][name].ravel()
+        got = tgn[k * vc:(k + 1) * vc]
+        assert np.max(np.abs(got - want)) <= 1e-8 * np.max(np.abs(want)), name
+    gt.destroy()
+
+
+def to_dev_1(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)

@@ -54,18 +54,18 @@ def test_noalloc_matches_cool_step_twice(dev):
     cells = W.workload(1, n=R.NOALLOC_MAX_CELLS)
     big, small = R.NOALLOC_MAX_CELLS, 4099
     tables = R.Tables.build(R.default_spec(64))
-    opts = R.default_opts()
+    opts = R.default_opts(passes=2)          # the two-pass step: its scratch is the static array
     print("noalloc: fresh tables, %d cells, then %d cells" % (big, small), flush=True)
 
     # fresh handle: no cell-blocked copy, so the call reads the node layout
     st = state_of(cells, dev, big)
     a = R.cool_step_noalloc(tables, st, DT, empty_out(big, dev), opts)
-    ref_global = R.cool_step(tables, st, DT, R.default_opts(variant="global"))
+    ref_global = R.cool_step(tables, st, DT, R.default_opts(variant="global", passes=2))
     torch.cuda.synchronize()
     check_same(a, ref_global, exact=True)
     # the explicit cell-blocked variant needs the copy, which this entry point never builds
     with pytest.raises(R.RadcoolError) as e:
-        R.cool_step_noalloc(tables, st, DT, empty_out(big, dev), R.default_opts(variant="cell"))
+        R.cool_step_noalloc(tables, st, DT, empty_out(big, dev), R.default_opts(variant="cell", passes=2))
     assert e.value.code == -5
 
     # rc_cool_step builds the copy; both entry points then read it
@@ -83,7 +83,7 @@ def test_noalloc_matches_cool_step_twice(dev):
     check_same(c, ref2, exact=True)
 
     # every scheme and the one-pass form go through it too
-    for kw in (dict(passes=1), dict(scheme="rates"), dict(scheme="explicit16")):
+    for kw in (dict(), dict(passes=1), dict(scheme="rates"), dict(scheme="explicit16")):
         o = R.default_opts(**kw)
         x = R.cool_step_noalloc(tables, st2, DT, empty_out(small, dev), o)
         y = R.cool_step(tables, st2, DT, o)
