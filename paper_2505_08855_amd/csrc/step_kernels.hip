@@ -47,9 +47,10 @@ __global__ __launch_bounds__(256, kStepWaves<SCHEME>) void k_step(Tab tab, StepP
   store(o, i, r);
 }
 
-// LDS-tiled variant: the fixed table coordinates of every cell, a workgroup
-// reduction of their range, staging of the box into LDS, then the scheme
-// (every thread of the workgroup reaches both barriers).
+// LDS-tiled variant: the fixed table coordinates of every cell, their range
+// over the workgroup (a min / max reduction across the lanes of each
+// wavefront, then across its wavefronts), staging of the box into LDS, then
+// the scheme (every thread of the workgroup reaches both barriers).
 // LDS per workgroup: 256 bytes per cell (64 KiB at 256 cells), so that
 // residency is set by registers, not LDS, at every workgroup size
 constexpr int kLdsPerCell = 256;
@@ -58,50 +59,66 @@ template <int SCHEME, class Base>
 __global__ __launch_bounds__(256, kStepWaves<SCHEME>) void k_step_lds(Base base, StepParams P, StateArgs s, OutArgs o,
                                                                      int64_t n) {
   extern __shared__ __align__(16) char lds[];
-  __shared__ LdsBox box;
+  __shared__ int wred[4][6];        // per wavefront: min and max of the three fixed indices
   const int tid = (int)threadIdx.x;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + tid;
-  if (tid < 3) {
-    box.lo[tid] = INT_MAX;
-    box.hi[tid] = INT_MIN;
-  }
-  __syncthreads();
+  // fixed table indices of this cell (N, B cooling cells, n_e Coulomb cell);
+  // invalid cells and cells past n read no table
+  int cl[3] = {INT_MAX, INT_MAX, INT_MAX}, ch[3] = {INT_MIN, INT_MIN, INT_MIN};
   if (i < n) {
     const double n_e = s.n_e[i], B = s.B[i], H = s.H[i];
-    // invalid cells read no table
     if (!(bad_input(n_e) || bad_input(s.T_e[i]) || bad_input(s.T_i[i]) || bad_input(B) || bad_input(H))) {
       const FixedCoords f = fixed_coords(P, n_e, B, H);
-      atomicMin(&box.lo[0], f.N.i); atomicMax(&box.hi[0], f.N.i);
-      atomicMin(&box.lo[1], f.B.i); atomicMax(&box.hi[1], f.B.i);
-      atomicMin(&box.lo[2], f.n.i); atomicMax(&box.hi[2], f.n.i);
+      cl[0] = ch[0] = f.N.i;
+      cl[1] = ch[1] = f.B.i;
+      cl[2] = ch[2] = f.n.i;
     }
   }
+  // range of the workgroup's cells: a min / max reduction inside each
+  // wavefront, then over the (at most four) wavefronts through LDS
+  const int wave = tid >> 6;
+  for (int d = 0; d < 3; ++d) {
+    cl[d] = wave_min(cl[d]);
+    ch[d] = wave_max(ch[d]);
+  }
+  if ((tid & 63) == 0)
+    for (int d = 0; d < 3; ++d) {
+      wred[wave][d] = cl[d];
+      wred[wave][3 + d] = ch[d];
+    }
   __syncthreads();
-  // the box is uniform over the workgroup: keep it in scalar registers; its
-  // extent is the cells' index range plus the upper corner of the highest cell
-  const int c1 = base.c1, k1 = base.k1, k2 = base.k2;
-  const long budget = (long)kLdsPerCell * blockDim.x;
+  const int nw = ((int)blockDim.x + 63) >> 6;
   int lo[3], hi[3];
   for (int d = 0; d < 3; ++d) {
-    lo[d] = __builtin_amdgcn_readfirstlane(box.lo[d]);
-    hi[d] = __builtin_amdgcn_readfirstlane(box.hi[d]);
+    int a = wred[0][d], b = wred[0][3 + d];
+    for (int w = 1; w < nw; ++w) {
+      a = min(a, wred[w][d]);
+      b = max(b, wred[w][3 + d]);
+    }
+    // uniform over the workgroup: keep it in scalar registers
+    lo[d] = __builtin_amdgcn_readfirstlane(a);
+    hi[d] = __builtin_amdgcn_readfirstlane(b);
   }
+  // the box extent is the cells' index range plus the upper corner of the
+  // highest cell; cooling nodes hold the solver's {brem, se} pair (8 bytes)
+  const int c1 = base.c1, k1 = base.k1, k2 = base.k2;
+  const long budget = (long)kLdsPerCell * blockDim.x;
   int dN = 0, dB = 0, dn = 0;
   if (hi[0] >= lo[0]) {
     dN = hi[0] - lo[0] + 2;
     dB = hi[1] - lo[1] + 2;
-    if ((long)dN * c1 * dB * (long)sizeof(float4) > budget) dN = dB = 0;
+    if ((long)dN * c1 * dB * (long)sizeof(float2) > budget) dN = dB = 0;
     dn = hi[2] - lo[2] + 2;
     // the Coulomb box is staged only beside a staged cooling box
-    if (dN == 0 || (long)dN * c1 * dB * (long)sizeof(float4) + (long)dn * k1 * k2 * (long)sizeof(float) > budget)
+    if (dN == 0 || (long)dN * c1 * dB * (long)sizeof(float2) + (long)dn * k1 * k2 * (long)sizeof(float) > budget)
       dn = 0;
   }
-  float4* cool_l = (float4*)lds;
-  float* coul_l = (float*)(lds + (size_t)dN * c1 * dB * sizeof(float4));
+  float2* cool_l = (float2*)lds;
+  float* coul_l = (float*)(lds + (size_t)dN * c1 * dB * sizeof(float2));
   const int vcool = dN * c1 * dB;
   for (int k = tid; k < vcool; k += (int)blockDim.x) {
     const int b = k % dB, t = (k / dB) % c1, a = k / (dB * c1);
-    cool_l[k] = base.cool_at(lo[0] + a, t, lo[1] + b);
+    cool_l[k] = brem_se(base.cool_at(lo[0] + a, t, lo[1] + b));
   }
   const int vcoul = dn * k1 * k2;
   for (int k = tid; k < vcoul; k += (int)blockDim.x) {
