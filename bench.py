@@ -97,7 +97,7 @@ SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD",
 ISSUE_PEAK = 1024 * 2.4e9 / 4 / 1e9     # G wave64 VALU instructions/s: 1024 SIMDs, one per 4 cycles at 2.4 GHz
 
 
-def counters_summary(fetch_dir, write_dir, sq_dir=None):
+def counters_summary(fetch_dir, write_dir, sq_dir=None, tcc_dir=None):
     """Markdown summary of the FETCH_SIZE / WRITE_SIZE passes (and an optional
     pass of SQ instruction counters) with the traffic record."""
     fetch = read_counters(fetch_dir, "FETCH_SIZE")
@@ -134,7 +134,7 @@ def counters_summary(fetch_dir, write_dir, sq_dir=None):
     print()
     if sq_dir:
         sq = {c: read_counters(sq_dir, c) for c in SQ_COUNTERS}
-        kernels = sorted(k for k in sq["SQ_WAVES"] if STEP_KERNELS.search(k))
+        kernels = sorted(sq["SQ_WAVES"], key=lambda k: -np.mean(sq["GRBM_GUI_ACTIVE"].get(k, [0.0])))
         print("| kernel | waves | VALU / wave | SALU / wave | VMEM reads / wave | VALU busy (of issue capacity) "
               "| wait / wave cycles | time from GRBM_GUI_ACTIVE |")
         print("|---|---|---|---|---|---|---|---|")
@@ -145,14 +145,27 @@ def counters_summary(fetch_dir, write_dir, sq_dir=None):
             # GRBM_GUI_ACTIVE counts GPU-busy cycles summed over the 8 XCDs
             t = m["GRBM_GUI_ACTIVE"] / 8 / 2.4e9
             cap = 1024 * m["GRBM_GUI_ACTIVE"] / 8 / 4
-            valu_step += m["SQ_INSTS_VALU"]
+            if STEP_KERNELS.search(k):
+                valu_step += m["SQ_INSTS_VALU"]
+            if t < 1e-5:
+                continue
             print("| %s | %d | %.0f | %.0f | %.1f | %.2f | %.3f | %.3f ms |" % (
-                k.split("(")[0][:60], waves, m["SQ_INSTS_VALU"] / waves, m["SQ_INSTS_SALU"] / waves,
+                short_name(k)[:60], waves, m["SQ_INSTS_VALU"] / waves, m["SQ_INSTS_SALU"] / waves,
                 m["SQ_INSTS_VMEM_RD"] / waves, m["SQ_INSTS_VALU"] / cap, m["SQ_WAIT_INST_ANY"] / m["SQ_WAVE_CYCLES"],
                 t * 1e3))
         rec["valu_insts_per_step"] = valu_step
         print()
-        print("VALU instructions per step (all its launches): %.4g" % valu_step)
+        print("VALU instructions per Newton step (all its launches): %.4g" % valu_step)
+        print()
+    if tcc_dir:
+        hit, miss = read_counters(tcc_dir, "TCC_HIT_sum"), read_counters(tcc_dir, "TCC_MISS_sum")
+        print("| kernel | L2 (TCC) hits / dispatch | misses / dispatch | hit rate |")
+        print("|---|---|---|---|")
+        for k in sorted(hit, key=lambda k: -np.mean(miss.get(k, [0.0]))):
+            h, m_ = float(np.mean(hit[k])), float(np.mean(miss.get(k, [0.0])))
+            if h + m_ < 1e5:
+                continue
+            print("| %s | %.4g | %.4g | %.3f |" % (short_name(k), h, m_, h / (h + m_)))
         print()
     print("traffic-record: " + json.dumps(rec))
 
@@ -187,6 +200,20 @@ def valu_roofline(ms):
             "frac": achieved / ISSUE_PEAK, "source": os.path.relpath(TRAFFIC_SUMMARY, ROOT)}
 
 
+def short_name(name):
+    """A kernel's demangled name without its parameter list."""
+    name = name.replace("(anonymous namespace)::", "")
+    depth = 0
+    for k, ch in enumerate(name):
+        if ch in "<":
+            depth += 1
+        elif ch in ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:k][:80]
+    return name[:80]
+
+
 def trace_summary(folder, skip):
     """Per-kernel durations of a rocprofv3 --kernel-trace folder over the
     dispatches after the first `skip` of each kernel."""
@@ -208,11 +235,14 @@ def trace_summary(folder, skip):
         d2 = d[skip:] if len(d) > skip else d
         out.append((float(np.mean(d2)), name, wg, len(d2), len(d) - len(d2), float(np.min(d2)), float(np.max(d2))))
     for avg, name, wg, n, sk, lo, hi in sorted(out, reverse=True):
-        print("| `%s` | %d | %d | %d | %.1f | %.1f | %.1f |" % (name.split("(")[0][:70], wg, n, sk, avg, lo, hi))
-    step = [o for o in out if STEP_KERNELS.search(o[1])]
-    if step:
-        print()
-        print("Newton step (sum of the averages of its launches): %.1f us" % sum(o[0] for o in step))
+        print("| `%s` | %d | %d | %d | %.1f | %.1f | %.1f |" % (short_name(name), wg, n, sk, avg, lo, hi))
+    one = [o for o in out if "k_step<0, rc::CellTab>" in o[1] and o[2] == 64]
+    two = [o for o in out if re.search(r"k_newton_first<rc::CellTab>|k_tile_sort|k_newton_resume<rc::CellTab>", o[1])]
+    print()
+    if one:
+        print("Newton step, one kernel (k_step<0, CellTab>, 64-thread workgroups): %.1f us" % one[0][0])
+    if two:
+        print("Newton step, two-pass form (sum of the averages of its launches): %.1f us" % sum(o[0] for o in two))
 
 
 def parse():
@@ -234,7 +264,8 @@ def parse():
                    help="first run a plain 512 MiB device copy (known HBM traffic) for counter calibration")
     p.add_argument("--no-precision", action="store_true")
     p.add_argument("--counters", nargs="+", metavar="DIR",
-                   help="FETCH_DIR WRITE_DIR [SQ_DIR]: summarise rocprofv3 --pmc folders instead of benchmarking")
+                   help="FETCH_DIR WRITE_DIR [SQ_DIR [TCC_DIR]]: summarise rocprofv3 --pmc folders instead of "
+                        "benchmarking")
     p.add_argument("--trace-summary", metavar="DIR", help="summarise a rocprofv3 --kernel-trace folder")
     p.add_argument("--skip", type=int, default=0, help="--trace-summary: dispatches of each kernel to skip")
     p.add_argument("--cpu-leg", nargs=2, metavar=("JOBS", "OUT"), help=argparse.SUPPRESS)
@@ -265,6 +296,11 @@ def time_steps(R, torch, tables, state, dt, opts, out, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return ev0.elapsed_time(ev1) / steps, wall
+
+
+def progress(msg):
+    """A progress line on stderr (the JSON result is the only line on stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def rel_errs(gpu, ref):
@@ -498,8 +534,8 @@ def main():
     if args.cpu_leg:
         return cpu_leg(*args.cpu_leg)
     if args.counters:
-        if len(args.counters) not in (2, 3):
-            raise SystemExit("--counters FETCH_DIR WRITE_DIR [SQ_DIR]")
+        if len(args.counters) not in (2, 3, 4):
+            raise SystemExit("--counters FETCH_DIR WRITE_DIR [SQ_DIR [TCC_DIR]]")
         return counters_summary(*args.counters)
     if args.trace_summary:
         return trace_summary(args.trace_summary, args.skip)
@@ -538,6 +574,7 @@ def main():
     out["status"] = torch.empty(n, dtype=torch.uint8, device=dev)
     opts = R.default_opts(variant=args.variant, scheme=args.scheme, passes=args.passes)
     ms, wall = time_steps(R, torch, tables, state, dt, opts, out, args.steps, args.warmup)
+    progress("timed step: %.4f ms over %d steps" % (ms, args.steps))
     table_bytes = 4 * 4 * table_n ** 3
     algo_bytes = BYTES_PER_CELL * n + table_bytes
     achieved = algo_bytes / (ms * 1e-3) / 1e9
@@ -591,6 +628,7 @@ def main():
                 var[name] = {"ms": vms, "Gcell_per_s": n / (vms * 1e-3) / 1e9}
             except R.RadcoolError as e:
                 var[name] = {"error": str(e)}
+            progress("variant %s done" % name)
         # the upstream inputs and the radiation-pressure correction over the same
         # cell count: elementwise kernels, 48 and 33 algorithmic bytes per cell
         rng = torch.Generator(device=dev).manual_seed(W.SEED_BASE)
@@ -691,6 +729,7 @@ def main():
         torch.cuda.synchronize()
         bms = e0.elapsed_time(e1) / 3
         var["backward_newton"] = {"ms": bms, "Gcell_per_s": n / (bms * 1e-3) / 1e9}
+        progress("elementwise kernels, 4-D table, bfloat16 tables and adjoint done")
         del tg, c, cot
         res["variants"] = var
         # the timed configuration again, so that the outputs below are its own
@@ -701,8 +740,10 @@ def main():
     tables.destroy()
     torch.cuda.empty_cache()
     if not args.no_variants and not args.no_blocks:
+        progress("building the batched workload")
         rep, fin = blocks_variant(args, R, W, torch, dev, jobs)
         res["variants"]["batched_blocks"] = rep
+        progress("batched form done")
         finishers.append(fin)
         torch.cuda.empty_cache()
     if not args.no_precision:
@@ -710,6 +751,7 @@ def main():
         res["precision"] = rep
         finishers.append(fin)
         res["accuracy"] = accuracy_report(R, torch, dev)
+        progress("precision and accuracy reports done")
     if not args.no_cpu_baseline:
         idx = np.sort(np.random.default_rng(20250513).choice(n, size=min(args.sample, n), replace=False))
         kind = "explicit16" if args.scheme == "explicit16" else "rates" if args.scheme == "rates" else "be"
@@ -717,6 +759,7 @@ def main():
                         "cells": [cells[f][idx] for f in W.FIELDS]})
         c0 = W.workload(0)
         jobs.insert(1, {"name": "iid32", "kind": kind, "table_n": 64, "dt": dt, "cells": [c0[f] for f in W.FIELDS]})
+        progress("oracle leg on the host cores")
         summary, outs = run_cpu_leg(jobs)
         sj, fj = summary["jobs"]["sample"], summary["jobs"]["iid32"]
         res["cpu_baseline"] = {

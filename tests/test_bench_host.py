@@ -75,7 +75,13 @@ def test_trace_summary_skips_warmup(tmp_path, capsys):
                 t += 10000
     bench.trace_summary(str(d), 1)
     out = capsys.readouterr().out
-    assert "Newton step (sum of the averages of its launches): 1.0 us" in out
+    assert "Newton step, two-pass form (sum of the averages of its launches): 1.0 us" in out
+    assert "| `void rc::k_newton_first<rc::CellTab>` | 64 | 2 | 1 | 0.5 |" in out
+
+
+def test_short_name_drops_the_parameter_list():
+    assert bench.short_name("rc::(anonymous namespace)::k_nodes4d(rc_axes4, float*)") == "rc::k_nodes4d"
+    assert bench.short_name("void rc::k_step<0, rc::CellTab>(rc::CellTab, long)") == "void rc::k_step<0, rc::CellTab>"
 
 
 def test_traffic_record_is_ignored_for_other_sources(monkeypatch):
