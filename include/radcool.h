@@ -398,7 +398,11 @@ typedef struct {
  * Q_cc add their direct derivatives.  RC_SCHEME_RATES is supported (T' = T);
  * RC_SCHEME_EXPLICIT16, the DIRECT variant and tables of the literal Compton
  * exponent give RC_EUNSUPPORTED.  fwd must hold the outputs of a
- * forward call with the same tables, state, dt and options.  With table
+ * forward call with the same tables, state, dt and options.  Table reads
+ * follow opts->variant as in rc_cool_step: AUTO and CELL read FP32 tables
+ * through the cell-blocked copy (a call that finds it missing builds it:
+ * allocates and synchronizes its stream), GLOBAL and LDS the node layout;
+ * every variant gives the same gradients.  With table
  * gradients the call keeps device scratch in the table handle: two records
  * per cell (about 160 bytes per cell) plus 24 doubles per table cell, allocated
  * (hipMalloc) on the first call and whenever n grows past what it holds;

@@ -345,6 +345,16 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
   const int64_t grid = (n + block - 1) / block;
   if (grid > 0x7fffffffLL) return set_error(RC_EINVAL, "rc_cool_step_backward: n too large for one launch");
   hipStream_t hs = (hipStream_t)stream;
+  // table reads: AUTO takes FP32 tables through the cell-blocked copy, as the
+  // forward step does (built here if no call has built it yet), CELL requires
+  // it; the other variants read the node layout
+  const bool cells = opts->variant == RC_VARIANT_CELL ||
+                     (opts->variant == RC_VARIANT_AUTO && t->spec.value_dtype == RC_VALUE_F32);
+  if (cells && (st = ensure_cells(t, hs)) != RC_OK) return st;
+  const auto with_bwd_tab = [&](auto&& f) {
+    if (cells) return f(cell_tab(t));
+    return with_tab(t, f);
+  };
   a.g_cool_cells = a.g_coul_cells = nullptr;
   a.key_cool = a.key_coul = a.cnt_cool = a.cnt_coul = nullptr;
   a.rec_cool = a.rec_coul = nullptr;
@@ -390,7 +400,7 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
     unsigned* nheavy = heavy_coul + mk;   // [cooling, Coulomb]
     hipLaunchKernelGGL(k_zero_u32, dim3(4096), dim3(256), 0, hs, a.cnt_cool, mc + mk);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, hs, nheavy, 2L);
-    with_tab(t, [&](auto tab) {
+    with_bwd_tab([&](auto tab) {
       hipLaunchKernelGGL((k_backward<decltype(tab), true>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, a, n);
       return 0;
     });
@@ -415,7 +425,7 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
     hipLaunchKernelGGL(k_finish_cells, dim3(4096), dim3(256), 0, hs, a.o_tab, (const double*)a.g_cool_cells,
                        (const double*)a.g_coul_cells, ca.n[0], ca.n[1], ca.n[2], ka.n[0], ka.n[1], ka.n[2]);
   } else {
-    with_tab(t, [&](auto tab) {
+    with_bwd_tab([&](auto tab) {
       hipLaunchKernelGGL((k_backward<decltype(tab), false>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, a, n);
       return 0;
     });

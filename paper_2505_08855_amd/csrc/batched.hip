@@ -125,9 +125,7 @@ hipError_t launch_batched(int scheme, const rc_tables_s* t, bool cells, const St
     return 0;
   };
   if (cells) {
-    const rc_table_spec& sp = t->spec;
-    launch(CellTab{(const float4*)t->d_cool, (const float*)t->d_coul, (const float2*)t->d_cool_cells,
-                   (const float*)t->d_coul_cells, sp.cool.n[1], sp.cool.n[2], sp.coul.n[1], sp.coul.n[2]});
+    launch(cell_tab(t));
   } else {
     with_tab(t, launch);
   }

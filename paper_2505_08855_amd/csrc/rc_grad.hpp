@@ -44,6 +44,8 @@ RC_HD CoolPoint cool_point(const Tab& tab, const StepParams& P, double u0, doubl
   CoolPoint r;
   double yb = 0.0, yse = 0.0;
   double gb[3] = {0.0, 0.0, 0.0}, gse[3] = {0.0, 0.0, 0.0};
+  float2 v[8];                           // the solver's {brem, se} pairs, corner (a, b, m) at 4a + 2b + m
+  tab.cool8(c0.i, c1.i, c2.i, v);
   int k = 0;
   for (int a = 0; a < 2; ++a) {
     const double wa = a ? c0.t : 1.0 - c0.t, da = a ? 1.0 : -1.0;
@@ -51,10 +53,8 @@ RC_HD CoolPoint cool_point(const Tab& tab, const StepParams& P, double u0, doubl
       const double wb = b ? c1.t : 1.0 - c1.t, db = b ? 1.0 : -1.0;
       for (int m = 0; m < 2; ++m, ++k) {
         const double wm = m ? c2.t : 1.0 - c2.t, dm = m ? 1.0 : -1.0;
-        const float4 p = tab.cool_at(c0.i + a, c1.i + b, c2.i + m);
         const double w = wa * wb * wm;
-        const float2 q = brem_se(p);     // the solver's {brem, se} pair
-        const double vb = q.x, vse = q.y;
+        const double vb = v[k].x, vse = v[k].y;
         yb += w * vb;
         yse += w * vse;
         const double g0 = da * wb * wm, g1 = wa * db * wm, g2 = wa * wb * dm;
@@ -86,6 +86,8 @@ RC_HD CoulPoint coul_point(const Tab& tab, const StepParams& P, double u0, doubl
   const Coord c0 = axis_coord(u0, P.g->ax[3]), c1 = axis_coord(u1, P.g->ax[4]), c2 = axis_coord(u2, P.g->ax[5]);
   CoulPoint r;
   double y = 0.0, g[3] = {0.0, 0.0, 0.0};
+  float cv[8];
+  tab.coul8(c0.i, c1.i, c2.i, cv);
   int k = 0;
   for (int a = 0; a < 2; ++a) {
     const double wa = a ? c0.t : 1.0 - c0.t, da = a ? 1.0 : -1.0;
@@ -93,7 +95,7 @@ RC_HD CoulPoint coul_point(const Tab& tab, const StepParams& P, double u0, doubl
       const double wb = b ? c1.t : 1.0 - c1.t, db = b ? 1.0 : -1.0;
       for (int m = 0; m < 2; ++m, ++k) {
         const double wm = m ? c2.t : 1.0 - c2.t, dm = m ? 1.0 : -1.0;
-        const double v = tab.coul_at(c0.i + a, c1.i + b, c2.i + m);
+        const double v = cv[k];
         const double w = wa * wb * wm;
         y += w * v;
         g[0] += da * wb * wm * v; g[1] += wa * db * wm * v; g[2] += wa * wb * dm * v;

@@ -71,4 +71,11 @@ auto with_tab(const rc_tables_s* t, F&& f) {
                      s.coul.n[2]});
 }
 
+// The accessor of t's cell-blocked copy (ensure_cells has built it).
+inline CellTab cell_tab(const rc_tables_s* t) {
+  const rc_table_spec& s = t->spec;
+  return CellTab{(const float4*)t->d_cool, (const float*)t->d_coul, (const float2*)t->d_cool_cells,
+                 (const float*)t->d_coul_cells, s.cool.n[1], s.cool.n[2], s.coul.n[1], s.coul.n[2]};
+}
+
 }  // namespace rc

@@ -468,9 +468,7 @@ rc_status cool_step_impl(rc_tables t, const rc_state* state, int64_t n, double d
   if (two_pass && variant == RC_VARIANT_CELL) {
     st = noalloc ? RC_OK : ensure_cells(t, hs);
     if (st != RC_OK) return st;
-    const rc_table_spec& sp = t->spec;
-    st = launch2(CellTab{(const float4*)t->d_cool, (const float*)t->d_coul, (const float2*)t->d_cool_cells,
-                         (const float*)t->d_coul_cells, sp.cool.n[1], sp.cool.n[2], sp.coul.n[1], sp.coul.n[2]});
+    st = launch2(cell_tab(t));
     if (st != RC_OK) return st;
   } else if (two_pass) {
     st = with_tab(t, launch2);
@@ -480,9 +478,7 @@ rc_status cool_step_impl(rc_tables t, const rc_state* state, int64_t n, double d
   } else if (variant == RC_VARIANT_CELL) {
     st = noalloc ? RC_OK : ensure_cells(t, hs);
     if (st != RC_OK) return st;
-    const rc_table_spec& sp = t->spec;
-    st = launch(CellTab{(const float4*)t->d_cool, (const float*)t->d_coul, (const float2*)t->d_cool_cells,
-                        (const float*)t->d_coul_cells, sp.cool.n[1], sp.cool.n[2], sp.coul.n[1], sp.coul.n[2]});
+    st = launch(cell_tab(t));
     if (st != RC_OK) return st;
   } else if (variant == RC_VARIANT_LDS) {
     // workgroups of 256 cells (or opts.block) share one staged box
