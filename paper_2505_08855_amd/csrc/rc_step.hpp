@@ -357,7 +357,7 @@ struct CellSolver {
     const double vb = fexp2(Ab + Sb * t);            // Q_brem
     const double vs = fexp2(Ase + Sse * t);          // eta Q_syn
     const double qthin = vb + vs;
-    const double dlq = kLn2 * g * fdiv(vb * Sb + vs * Sse, qthin);
+    const double dlq = kLn2 * g * fdiv_d(vb * Sb + vs * Sse, qthin);
     const double x2 = x * x;
     const double ta = fdiv(H * qthin, 4.0 * kSigmaSB * x2 * x2);
     const double D = 1.0 + kSqrt3 * ta + 1.5 * ta * (ta + tau_sca);
@@ -400,7 +400,7 @@ struct CellSolver {
       // x == T_i: z = T_i solves E2; implicit derivative dz/dx = dt K / (c + dt K)
       K = kcoul_at(ce, ci0, &dlx, &dlz);
       if (K_first) *K_first = K;
-      *dzdx = fdiv(dt * K, c + dt * K);
+      *dzdx = fdiv_d(dt * K, c + dt * K);
       return lo;
     }
     double dEz = c;
@@ -408,10 +408,10 @@ struct CellSolver {
       K = it == 0 ? kcoul_at(ce, ci0, &dlx, &dlz) : kcoul(ce, z, &dlx, &dlz);
       if (it == 0 && K_first) *K_first = K;
       const double E = c * (z - T_i) + dt * (z - x) * K;
-      dEz = c + dt * K + dt * (z - x) * K * fdiv(dlz, z);
+      dEz = c + dt * K + dt * (z - x) * K * fdiv_d(dlz, z);
       if (E == 0.0) break;                  // z is an exact root
       if (E < 0.0) lo = z; else hi = z;
-      const double dz = -fdiv(E, dEz);
+      const double dz = -fdiv_d(E, dEz);
       // converged: Newton converges quadratically, so after a step below
       // 1e-6 z the remaining error is of order 1e-12 z (on the iid cells the
       // solution moves by at most 2.5e-14 against a 1e-8 threshold, which
@@ -423,8 +423,8 @@ struct CellSolver {
       z = zn;
       if (hi - lo <= 1e-15 * z) break;
     }
-    const double dEx = -dt * K + dt * (z - x) * K * fdiv(dlx, x);
-    *dzdx = -fdiv(dEx, dEz);
+    const double dEx = -dt * K + dt * (z - x) * K * fdiv_d(dlx, x);
+    *dzdx = -fdiv_d(dEx, dEz);
     return z;
   }
 
@@ -460,20 +460,22 @@ struct CellSolver {
     const double numer = c * ((x - T_e) + (*z - T_i)) + dt * q;
     const double cx = c * x * (1.0 + dzdx);
     const double cS = c * (T_e + T_i);
-    *dG = fdiv(cx + dt * dq, cS + numer);
+    *dG = fdiv_d(cx + dt * dq, cS + numer);
     *q_out = q;
     *dzdx_out = dzdx;
     *ds3 = __builtin_nan("");
-    const double G = flog1p(fdiv(numer, cS));
+    const double G = flog1p(fdiv_d(numer, cS));
     if (mode == 1) {
       const double cxz = c * x * dzdx;
       double Pg = dt * q, Ng = 0.0, dP = dt * dq, dN = 0.0;
       if (x > T_e) { Pg += c * (x - T_e); dP += c * x; } else { Ng += c * (T_e - x); dN -= c * x; }
       if (*z > T_i) { Pg += c * (*z - T_i); dP += cxz; } else { Ng += c * (T_i - *z); dN -= cxz; }
       if (Pg > 0.0 && Ng > 0.0) {
-        const double iP = fdiv(1.0, Pg), iN = fdiv(1.0, Ng);
+        // 1 / Ng to full precision: near the root Pg / Ng is close to 1 and
+        // its logarithm is the step
+        const double iP = fdiv_d(1.0, Pg), iN = fdiv(1.0, Ng);
         const double dG3 = dP * iP - dN * iN;
-        if (dG3 > 0.0) *ds3 = -fdiv(flog(Pg * iN), dG3);
+        if (dG3 > 0.0) *ds3 = -fdiv_d(flog(Pg * iN), dG3);
       }
     } else if (mode == 2 && numer < 0.0 && *dG > 0.0 && *z < T_i) {
       // first step of a heating cell: the electrons' gain
@@ -482,10 +484,11 @@ struct CellSolver {
       // base 2 and relative to N0 = c (T_i - z):
       //   f(u) = log2(a (2^u - 1) + r 2^(p u)) - b0 u
       const double N0 = c * (T_i - *z);
-      const float a = (float)(c * x / N0), r = (float)(dt * q / N0);
-      const float p = q > 0.0 ? (float)(dq / q) : 0.0f;
-      const float b0 = (float)(-c * x * dzdx / N0);
-      float u = (float)(-G / (*dG * kLn2));
+      const double iN0 = fdiv_sp(1.0, N0);
+      const float a = (float)(c * x * iN0), r = (float)(dt * q * iN0);
+      const float p = q > 0.0 ? (float)fdiv_sp(dq, q) : 0.0f;
+      const float b0 = (float)(-c * x * dzdx * iN0);
+      float u = (float)fdiv_sp(-G, *dG * kLn2);
       for (int k = 0; k < 5; ++k) {
         const float e = fexp2_sp(u), eq = fexp2_sp(p * u);
         const float Pn = a * (e - 1.0f) + r * eq;
@@ -496,10 +499,11 @@ struct CellSolver {
     } else if (mode == 2 && numer > 0.0 && q > 0.0 && *dG > 0.0) {
       // in base 2: u = d / ln 2, f(u) = L + p u - log2(1 - 2^u + r0),
       // L = log2(dt q / A), r0 = R0 / A
-      const float p = (float)(dq / q);
-      const float L = flog2_sp((float)(dt * q / cx));
-      const float r0 = (float)(c * (T_i - *z) / cx);
-      float u = (float)(-G / (*dG * kLn2));
+      const double icx = fdiv_sp(1.0, cx);
+      const float p = (float)fdiv_sp(dq, q);
+      const float L = flog2_sp((float)(dt * q * icx));
+      const float r0 = (float)(c * (T_i - *z) * icx);
+      float u = (float)fdiv_sp(-G, *dG * kLn2);
       for (int k = 0; k < 4; ++k) {
         const float e = fexp2_sp(u);
         const float R = (1.0f - e) + r0;
@@ -630,7 +634,7 @@ struct CellSolver {
       // that overshoots less -- the longer on the convex side above the root,
       // the shorter below it, and the reverse for concave -- is the closer.
       const bool use3 = (ds3 == ds3);
-      const double dsG = -ns.G / ns.dG;
+      const double dsG = -fdiv_d(ns.G, ns.dG);
       double sn = s + dsG;
       if (use3) {
         // the model root is a single-precision estimate: taken only for a
