@@ -120,6 +120,17 @@ typedef struct {
   int32_t compton_exponent;  /* RC_COMPTON_DERIVED (default) or RC_COMPTON_LITERAL */
   int32_t theta_i_mass;      /* RC_THETA_I_MP (default) or RC_THETA_I_ME */
   int32_t reserved;          /* must be 0 */
+  void* external_storage;    /* NULL (default): the library allocates and owns the
+                                device memory of the tables.  Otherwise caller-owned
+                                device memory on the current device, 256-byte aligned,
+                                of at least rc_tables_storage_bytes(spec) bytes, that
+                                rc_build_tables / rc_tables_import put the tables into
+                                (geometry, node tables and, for FP32 tables, the
+                                cell-blocked copy, built at once instead of on first
+                                use); rc_tables_destroy does not free it, and the
+                                caller keeps it alive and unmodified until then.
+                                Saved table files never hold it. */
+  uint64_t external_bytes;   /* size of external_storage in bytes (0 when it is NULL) */
 } rc_table_spec;
 
 typedef struct rc_tables_s* rc_tables;   /* opaque, library-owned device tables */
@@ -230,6 +241,15 @@ enum { RC_RATE_F64 = 0, RC_RATE_F32 = 1 };
  * m_p.  Returns RC_EINVAL for spec == NULL or n < 2. */
 rc_status rc_default_spec(rc_table_spec* spec, int32_t n);
 
+/* Device bytes the tables of *spec occupy, for spec->external_storage: the
+ * geometry record, the node tables (16 bytes per cooling node and 4 per
+ * Coulomb node for FP32 residuals; 8 and 2 for bfloat16) and, for FP32
+ * tables, the cell-blocked copy (64 bytes per cooling cell, 32 per Coulomb
+ * cell), each part 256-byte aligned.  Host only (no device call); the
+ * external_storage fields of *spec are ignored.  RC_EINVAL for an invalid
+ * spec or bytes == NULL. */
+rc_status rc_tables_storage_bytes(const rc_table_spec* spec, uint64_t* bytes);
+
 /* Fill *opts with: Newton scheme, AUTO variant, max_iter 60, block 0,
  * T_floor 1e6 K, tol 1e-12, passes 0, grid 0, FP64 rates. */
 rc_status rc_default_opts(rc_step_opts* opts);
@@ -237,8 +257,12 @@ rc_status rc_default_opts(rc_step_opts* opts);
 /* Build the four tables on the current device from the closed forms of Sec. II
  * (node values in FP64 on the GPU; a least-squares affine function of the node
  * indices is removed from each log2 table on the host and the residual is
- * stored in FP32, or in bfloat16 when spec->value_dtype says so).  Synchronous.  *out receives a new handle owned by the
- * caller (release with rc_tables_destroy). */
+ * stored in FP32, or in bfloat16 when spec->value_dtype says so).
+ * Synchronous.  *out receives a new handle owned by the caller (release with
+ * rc_tables_destroy).  With spec->external_storage the tables are put there;
+ * the node evaluation still takes temporary device memory (8 bytes per node,
+ * freed before the call returns).  RC_EINVAL for external storage that is
+ * too small, not 256-byte aligned or not device memory of the current device. */
 rc_status rc_build_tables(const rc_table_spec* spec, void* stream, rc_tables* out);
 
 /* Create tables from host data in the storage form: resid holds the FP32
@@ -248,7 +272,8 @@ rc_status rc_build_tables(const rc_table_spec* spec, void* stream, rc_tables* ou
  * value = c0 + c1 i0 + c2 i1 + c3 i2 + resid).  For RC_VALUE_BF16 the
  * residuals are rounded to bfloat16 (nearest, ties to even) on import, and
  * export returns the rounded values.  Synchronous; host buffers are only read
- * during the call. */
+ * during the call.  With spec->external_storage (checked as for
+ * rc_build_tables) the call allocates no device memory. */
 rc_status rc_tables_import(const rc_table_spec* spec, const float* resid, const double* coeffs,
                            void* stream, rc_tables* out);
 
@@ -259,9 +284,10 @@ rc_status rc_tables_export(rc_tables t, float* resid, double* coeffs);
 /* Spec of a table set and the number of residual values (sum over the four tables). */
 rc_status rc_tables_info(rc_tables t, rc_table_spec* spec, int64_t* n_values);
 
-/* Save to / load from a binary file: header (magic, version, spec), the
- * coefficients, the residuals and a 64-bit checksum of the payload.  Load
- * verifies the checksum (RC_EIO on mismatch). */
+/* Save to / load from a binary file: header (magic, version, spec without its
+ * external_storage fields), the coefficients, the residuals and a 64-bit
+ * checksum of the payload.  Load verifies the checksum (RC_EIO on mismatch)
+ * and returns library-owned tables. */
 rc_status rc_tables_save(rc_tables t, const char* path);
 rc_status rc_tables_load(const char* path, void* stream, rc_tables* out);
 

@@ -45,7 +45,25 @@ bool spec_ok(const rc_table_spec* s) {
   return s && axes_ok(s->cool) && axes_ok(s->coul) && std::isfinite(s->ln_lambda) && s->ln_lambda > 0.0 &&
          (s->value_dtype == RC_VALUE_F32 || s->value_dtype == RC_VALUE_BF16) &&
          (s->compton_exponent == RC_COMPTON_DERIVED || s->compton_exponent == RC_COMPTON_LITERAL) &&
-         (s->theta_i_mass == RC_THETA_I_MP || s->theta_i_mass == RC_THETA_I_ME) && s->reserved == 0;
+         (s->theta_i_mass == RC_THETA_I_MP || s->theta_i_mass == RC_THETA_I_ME) && s->reserved == 0 &&
+         (s->external_storage != nullptr || s->external_bytes == 0);
+}
+
+StorageLayout storage_layout(const rc_table_spec& s) {
+  const auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const bool bf = s.value_dtype == RC_VALUE_BF16;
+  const size_t vc = (size_t)volume(s.cool), vk = (size_t)volume(s.coul);
+  const size_t mc = (size_t)(s.cool.n[0] - 1) * (s.cool.n[1] - 1) * (s.cool.n[2] - 1);
+  const size_t mk = (size_t)(s.coul.n[0] - 1) * (s.coul.n[1] - 1) * (s.coul.n[2] - 1);
+  StorageLayout L;
+  L.cells = !bf;
+  L.geom = 0;
+  L.cool = up(sizeof(TableGeom));
+  L.coul = L.cool + up((bf ? 8 : 16) * vc);
+  L.cool_cells = L.coul + up((bf ? 2 : 4) * vk);
+  L.coul_cells = L.cool_cells + (L.cells ? up(8 * sizeof(float2) * mc) : 0);
+  L.total = L.coul_cells + (L.cells ? up(8 * sizeof(float) * mk) : 0);
+  return L;
 }
 
 int64_t volume(const rc_axes& a) { return (int64_t)a.n[0] * a.n[1] * a.n[2]; }
@@ -84,6 +102,19 @@ extern "C" rc_status rc_default_spec(rc_table_spec* spec, int32_t n) {
   spec->compton_exponent = RC_COMPTON_DERIVED;
   spec->theta_i_mass = RC_THETA_I_MP;
   spec->reserved = 0;
+  spec->external_storage = nullptr;
+  spec->external_bytes = 0;
+  return RC_OK;
+}
+
+extern "C" rc_status rc_tables_storage_bytes(const rc_table_spec* spec, uint64_t* bytes) {
+  if (!bytes) return fail(RC_EINVAL, "rc_tables_storage_bytes: bytes is NULL");
+  if (!spec) return fail(RC_EINVAL, "rc_tables_storage_bytes: spec is NULL");
+  rc_table_spec s = *spec;
+  s.external_storage = nullptr;
+  s.external_bytes = 0;
+  if (!spec_ok(&s)) return fail(RC_EINVAL, "rc_tables_storage_bytes: invalid table spec");
+  *bytes = (uint64_t)storage_layout(s).total;
   return RC_OK;
 }
 
@@ -201,21 +232,34 @@ rc_status upload(rc_tables_s* t, void* stream) {
   if (bf)
     for (int64_t i = 0; i < vk; ++i) packed16[4 * vc + i] = bf16_bits(t->resid[3 * vc + i]);
   fill_geom(t);
-  hipError_t e = hipMalloc(&t->d_geom, sizeof(TableGeom));
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(table geometry)");
+  hipError_t e = hipSuccess;
+  hipStream_t s = (hipStream_t)stream;
+  if (t->external) {
+    // the caller's storage: parts at the offsets of storage_layout
+    char* base = (char*)t->spec.external_storage;
+    const StorageLayout L = storage_layout(t->spec);
+    t->d_geom = (TableGeom*)(base + L.geom);
+    t->d_cool = base + L.cool;
+    t->d_coul = base + L.coul;
+  } else {
+    e = hipMalloc(&t->d_geom, sizeof(TableGeom));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(table geometry)");
+    e = hipMalloc(&t->d_cool, cool_bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(cooling tables)");
+    e = hipMalloc(&t->d_coul, coul_bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(Coulomb table)");
+  }
   e = hipMemcpy(t->d_geom, &t->geom, sizeof(TableGeom), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "table geometry upload");
-  e = hipMalloc(&t->d_cool, cool_bytes);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(cooling tables)");
-  e = hipMalloc(&t->d_coul, coul_bytes);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(Coulomb table)");
-  hipStream_t s = (hipStream_t)stream;
   const void* hc = bf ? (const void*)packed16.data() : (const void*)packed.data();
   const void* hk = bf ? (const void*)(packed16.data() + 4 * vc) : (const void*)(t->resid.data() + 3 * vc);
   e = hipMemcpyAsync(t->d_cool, hc, cool_bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(t->d_coul, hk, coul_bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "table upload");
+  // external storage of FP32 tables holds the cell-blocked copy too: built
+  // now, so that no later call allocates it
+  if (t->external && t->spec.value_dtype == RC_VALUE_F32) return ensure_cells(t, s);
   return RC_OK;
 }
 
@@ -257,8 +301,15 @@ rc_status ensure_cells(rc_tables_s* t, hipStream_t s) {
   const int64_t nc = (int64_t)(a.n[0] - 1) * (a.n[1] - 1) * (a.n[2] - 1) * 8;
   const int64_t nk = (int64_t)(k.n[0] - 1) * (k.n[1] - 1) * (k.n[2] - 1) * 8;
   void *dc = nullptr, *dk = nullptr;
-  hipError_t e = hipMalloc(&dc, sizeof(float2) * nc);
-  if (e == hipSuccess) e = hipMalloc(&dk, sizeof(float) * nk);
+  hipError_t e = hipSuccess;
+  if (t->external) {
+    const StorageLayout L = storage_layout(t->spec);
+    dc = (char*)t->spec.external_storage + L.cool_cells;
+    dk = (char*)t->spec.external_storage + L.coul_cells;
+  } else {
+    e = hipMalloc(&dc, sizeof(float2) * nc);
+    if (e == hipSuccess) e = hipMalloc(&dk, sizeof(float) * nk);
+  }
   if (e == hipSuccess) {
     const auto grid = [](int64_t m) { return (unsigned)std::min<int64_t>((m + 255) / 256, 1 << 16); };
     hipLaunchKernelGGL(k_cells_cool, dim3(grid(nc)), dim3(256), 0, s, (const float4*)t->d_cool, (float2*)dc, a.n[0],
@@ -270,8 +321,8 @@ rc_status ensure_cells(rc_tables_s* t, hipStream_t s) {
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
   if (e != hipSuccess) {
-    if (dc) (void)hipFree(dc);
-    if (dk) (void)hipFree(dk);
+    if (dc && !t->external) (void)hipFree(dc);
+    if (dk && !t->external) (void)hipFree(dk);
     return hip_fail(e, "building the cell-blocked tables");
   }
   t->d_cool_cells = dc;
@@ -281,14 +332,16 @@ rc_status ensure_cells(rc_tables_s* t, hipStream_t s) {
 
 void destroy_tables(rc_tables_s* t) {
   if (!t) return;
-  if (t->d_geom) (void)hipFree(t->d_geom);
-  if (t->d_cool) (void)hipFree(t->d_cool);
-  if (t->d_coul) (void)hipFree(t->d_coul);
+  if (!t->external) {
+    if (t->d_geom) (void)hipFree(t->d_geom);
+    if (t->d_cool) (void)hipFree(t->d_cool);
+    if (t->d_coul) (void)hipFree(t->d_coul);
+    if (t->d_cool_cells) (void)hipFree(t->d_cool_cells);
+    if (t->d_coul_cells) (void)hipFree(t->d_coul_cells);
+  }
   if (t->d_counter) (void)hipFree(t->d_counter);
   if (t->d_gscratch) (void)hipFree(t->d_gscratch);
   if (t->d_step_scratch) (void)hipFree(t->d_step_scratch);
-  if (t->d_cool_cells) (void)hipFree(t->d_cool_cells);
-  if (t->d_coul_cells) (void)hipFree(t->d_coul_cells);
   t->magic = 0;
   delete t;
 }
@@ -299,6 +352,23 @@ rc_status new_tables(const rc_table_spec* spec, rc_tables_s** out) {
   t->spec = *spec;
   t->magic = kTablesMagic;
   if (hipGetDevice(&t->device) != hipSuccess) t->device = -1;
+  if (spec->external_storage) {
+    // caller-owned device memory on this device, aligned and large enough
+    const StorageLayout L = storage_layout(*spec);
+    hipPointerAttribute_t pa{};
+    const bool on_device = hipPointerGetAttributes(&pa, spec->external_storage) == hipSuccess &&
+                           pa.type == hipMemoryTypeDevice && pa.device == t->device;
+    (void)hipGetLastError();   // a host pointer leaves an error behind; the message below reports it
+    const char* bad = !on_device ? "external_storage is not device memory of the current device"
+                    : ((uintptr_t)spec->external_storage & 255) ? "external_storage is not 256-byte aligned"
+                    : spec->external_bytes < L.total ? "external_bytes is below rc_tables_storage_bytes(spec)"
+                    : nullptr;
+    if (bad) {
+      delete t;
+      return fail(RC_EINVAL, bad);
+    }
+    t->external = true;
+  }
   const int64_t vc = volume(spec->cool), vk = volume(spec->coul);
   try {
     t->resid.assign((size_t)(3 * vc + vk), 0.0f);
@@ -478,7 +548,7 @@ extern "C" rc_status rc_tables_destroy(rc_tables t) {
 
 namespace {
 
-constexpr char kFileMagic[8] = {'R', 'C', 'T', 'A', 'B', 'L', 'E', '3'};
+constexpr char kFileMagic[8] = {'R', 'C', 'T', 'A', 'B', 'L', 'E', '4'};
 
 // FNV-1a, 64 bit, over the payload bytes
 uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
@@ -498,11 +568,15 @@ extern "C" rc_status rc_tables_save(rc_tables t, const char* path) {
   FILE* f = std::fopen(path, "wb");
   if (!f) return fail(RC_EIO, std::string("rc_tables_save: cannot open ") + path);
   const uint64_t n = t->resid.size();
+  // the file holds the tables, not where they lived
+  rc_table_spec spec = t->spec;
+  spec.external_storage = nullptr;
+  spec.external_bytes = 0;
   uint64_t h = 1469598103934665603ULL;
-  h = fnv1a(&t->spec, sizeof(t->spec), h);
+  h = fnv1a(&spec, sizeof(spec), h);
   h = fnv1a(t->coef, sizeof(t->coef), h);
   h = fnv1a(t->resid.data(), sizeof(float) * n, h);
-  bool ok = std::fwrite(kFileMagic, 1, 8, f) == 8 && std::fwrite(&t->spec, sizeof(t->spec), 1, f) == 1 &&
+  bool ok = std::fwrite(kFileMagic, 1, 8, f) == 8 && std::fwrite(&spec, sizeof(spec), 1, f) == 1 &&
             std::fwrite(&n, sizeof(n), 1, f) == 1 && std::fwrite(t->coef, sizeof(t->coef), 1, f) == 1 &&
             std::fwrite(t->resid.data(), sizeof(float), n, f) == n && std::fwrite(&h, sizeof(h), 1, f) == 1;
   ok = (std::fclose(f) == 0) && ok;

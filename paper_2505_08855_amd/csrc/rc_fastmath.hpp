@@ -31,7 +31,6 @@ constexpr double kLog2E = 0x1.71547652b82fep+0;     // 1 / ln 2
 constexpr double kInvLn10 = 0x1.bcb7b1526e50ep-2;   // 1 / ln 10
 constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;  // sqrt(1/2)
 
-// ln x for finite x > 0
 // a / b for finite a and a finite nonzero b of normal magnitude: the
 // reciprocal instruction refined by two Newton steps, then the quotient with
 // one residual correction; within an ulp of a / b.  The IEEE sequence adds
@@ -120,6 +119,7 @@ RC_HD float flog2_sp(float x) {
 #endif
 }
 
+// ln x for finite x > 0
 RC_HD double flog(double x) {
   int e;
   double m = frexp(x, &e);           // [1/2, 1)

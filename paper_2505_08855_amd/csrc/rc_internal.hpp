@@ -38,6 +38,9 @@ struct rc_tables_s {
   void* d_cool_cells = nullptr;
   void* d_coul_cells = nullptr;
   std::mutex cells_lock;
+  // geometry, node tables and cell-blocked copy live in the caller's
+  // spec.external_storage (not freed by the library)
+  bool external = false;
 };
 
 namespace rc {
@@ -46,6 +49,14 @@ rc_status set_error(rc_status s, const char* msg);
 rc_status hip_fail(hipError_t e, const char* what);
 bool handle_ok(rc_tables t);
 bool spec_ok(const rc_table_spec* s);
+
+// Offsets (bytes, each 256-aligned) of the parts of a table set's device
+// memory in external storage, and the total.
+struct StorageLayout {
+  size_t geom, cool, coul, cool_cells, coul_cells, total;
+  bool cells;           // FP32 tables: the cell-blocked copy is part of the storage
+};
+StorageLayout storage_layout(const rc_table_spec& s);
 int64_t volume(const rc_axes& a);
 void fill_axes(const rc_table_spec& s, AxisP ax[6]);
 // fill t->geom from t->spec and t->coef

@@ -25,7 +25,7 @@ VARIANTS = {"auto": 0, "global": 1, "lds": 2, "tex": 3, "direct": 4, "cell": 5}
 SCHEMES = {"newton": 0, "explicit16": 1, "rates": 2}
 
 EXPORTED = ("rc_default_spec", "rc_default_opts", "rc_build_tables", "rc_tables_import",
-            "rc_tables_export", "rc_tables_info", "rc_tables_save", "rc_tables_load",
+            "rc_tables_export", "rc_tables_info", "rc_tables_save", "rc_tables_load", "rc_tables_storage_bytes",
             "rc_tables_destroy", "rc_cool_step", "rc_cool_step_noalloc", "rc_constants", "rc_selftest_node_host",
             "rc_selftest_special_host", "rc_selftest_step_host", "rc_last_error",
             "rc_cool_step_backward", "rc_selftest_backward_host", "rc_cool_step_batched",
@@ -57,7 +57,8 @@ RATE_DTYPES = {"f64": 0, "f32": 1}
 class TableSpec(ctypes.Structure):
     _fields_ = [("cool", Axes), ("coul", Axes), ("ln_lambda", ctypes.c_double),
                 ("value_dtype", ctypes.c_int32), ("compton_exponent", ctypes.c_int32),
-                ("theta_i_mass", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("theta_i_mass", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("external_storage", ctypes.c_void_p), ("external_bytes", ctypes.c_uint64)]
 
 
 class State(ctypes.Structure):
@@ -137,6 +138,7 @@ def lib():
             "rc_tables_save": (i32, [vp, ctypes.c_char_p]),
             "rc_tables_load": (i32, [ctypes.c_char_p, vp, P(vp)]),
             "rc_tables_destroy": (i32, [vp]),
+            "rc_tables_storage_bytes": (i32, [P(TableSpec), P(ctypes.c_uint64)]),
             "rc_cool_step": (i32, [vp, P(State), i64, dbl, P(StepOpts), P(Out), vp]),
             "rc_cool_step_noalloc": (i32, [vp, P(State), i64, dbl, P(StepOpts), P(Out), vp]),
             "rc_constants": (i32, [vp, i32]),
@@ -239,11 +241,30 @@ def spec_sizes(spec):
     return vc, vk
 
 
+def storage_bytes(spec):
+    """Device bytes the tables of ``spec`` occupy in external storage."""
+    n = ctypes.c_uint64()
+    check(lib().rc_tables_storage_bytes(ctypes.byref(spec), ctypes.byref(n)))
+    return n.value
+
+
+def _with_storage(spec, storage):
+    """A copy of spec pointing at the device tensor ``storage`` (or spec itself)."""
+    if storage is None:
+        return spec
+    s = TableSpec()
+    ctypes.pointer(s)[0] = spec
+    s.external_storage = storage.data_ptr()
+    s.external_bytes = storage.numel() * storage.element_size()
+    return s
+
+
 class Tables:
     """Owning wrapper of an rc_tables handle."""
 
-    def __init__(self, handle):
+    def __init__(self, handle, storage=None):
         self._h = ctypes.c_void_p(handle)
+        self._storage = storage          # caller-owned device memory the tables live in
 
     @property
     def handle(self):
@@ -252,26 +273,30 @@ class Tables:
         return self._h
 
     @staticmethod
-    def build(spec=None, stream=None):
-        spec = spec if spec is not None else default_spec()
+    def build(spec=None, stream=None, storage=None):
+        """Build tables from the closed forms; ``storage`` (optional) is a
+        caller-owned device tensor of at least ``storage_bytes(spec)`` bytes
+        that the tables are put into (kept referenced by the returned object)."""
+        spec = _with_storage(spec if spec is not None else default_spec(), storage)
         h = ctypes.c_void_p()
         check(lib().rc_build_tables(ctypes.byref(spec), _stream_ptr(stream), ctypes.byref(h)))
-        return Tables(h.value)
+        return Tables(h.value, storage)
 
     @staticmethod
-    def from_storage(spec, resid, coeffs, stream=None):
+    def from_storage(spec, resid, coeffs, stream=None, storage=None):
         """Create tables from host FP32 residuals (all four tables back to back) and
-        FP64 coefficients (4 x 4)."""
+        FP64 coefficients (4 x 4); ``storage`` as for ``build``."""
         resid = np.ascontiguousarray(resid, dtype=np.float32).ravel()
         coeffs = np.ascontiguousarray(coeffs, dtype=np.float64).ravel()
         vc, vk = spec_sizes(spec)
         if resid.size != 3 * vc + vk or coeffs.size != 16:
             raise ValueError("storage arrays do not match the spec")
+        spec = _with_storage(spec, storage)
         h = ctypes.c_void_p()
         check(lib().rc_tables_import(ctypes.byref(spec), resid.ctypes.data_as(ctypes.c_void_p),
                                      coeffs.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream),
                                      ctypes.byref(h)))
-        return Tables(h.value)
+        return Tables(h.value, storage)
 
     @staticmethod
     def load(path, stream=None):

@@ -152,7 +152,8 @@ int main(void) {
   S(rc_axes); S(rc_table_spec); S(rc_state); S(rc_out); S(rc_step_opts); S(rc_block); S(rc_fwd);
   S(rc_cotangent); S(rc_grad); S(rc_disk_params); S(rc_coupling); S(rc_axes4);
   O(rc_table_spec, ln_lambda); O(rc_table_spec, value_dtype); O(rc_table_spec, compton_exponent);
-  O(rc_table_spec, theta_i_mass); O(rc_table_spec, reserved);
+  O(rc_table_spec, theta_i_mass); O(rc_table_spec, reserved); O(rc_table_spec, external_storage);
+  O(rc_table_spec, external_bytes);
   O(rc_step_opts, T_floor); O(rc_step_opts, tol); O(rc_step_opts, passes); O(rc_step_opts, grid);
   O(rc_step_opts, rate_dtype); O(rc_step_opts, reserved);
   O(rc_out, Q_rad); O(rc_out, status); O(rc_out, eta);
@@ -187,7 +188,7 @@ def test_struct_layouts_match_the_binding(tmp_path):
         elif len(parts) == 3:
             assert getattr(types[parts[0]], parts[1]).offset == int(parts[2]), (parts[0], parts[1])
             seen += 1
-    assert seen == 12 + 16
+    assert seen == 12 + 18
 
 
 def test_apply_cooling_rejects_bad_arguments(L):
@@ -231,3 +232,52 @@ def test_variant_names_match_the_header():
     op.variant = max(R.VARIANTS.values()) + 1
     assert L.rc_selftest_step_host(ctypes.byref(s), P(resid), P(co), *[P(x)] * 5, None, 1, 1e-8,
                                    ctypes.byref(op), None, None, None, None, None) == -1
+
+
+def _up(b):
+    return (b + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("n,dtype", [((64, 64, 64), "f32"), ((128, 128, 128), "f32"), ((5, 7, 9), "f32"),
+                                     ((64, 64, 64), "bf16"), ((5, 7, 9), "bf16")])
+def test_storage_bytes_is_the_layout_of_the_parts(L, n, dtype):
+    """rc_tables_storage_bytes: geometry record, node tables (16 / 4 bytes per
+    cooling / Coulomb node in FP32, 8 / 2 in bfloat16) and, for FP32, the
+    cell-blocked copy (64 / 32 bytes per table cell), each 256-byte aligned."""
+    ax = [(m, 0.0, 1.0) for m in n]
+    s = R.spec_from_axes(ax, ax[::-1], value_dtype=dtype)
+    vc = vk = n[0] * n[1] * n[2]
+    cells = (n[0] - 1) * (n[1] - 1) * (n[2] - 1)
+    bf = dtype == "bf16"
+    got = R.storage_bytes(s)
+    parts = [_up((8 if bf else 16) * vc), _up((2 if bf else 4) * vk)]
+    if not bf:
+        parts += [_up(64 * cells), _up(32 * cells)]
+    # the geometry record: one 256-byte-aligned slot ahead of the tables
+    assert got - sum(parts) in (256, 512)
+    assert got % 256 == 0
+    # the external fields of the spec do not enter the size
+    s.external_storage = 4096
+    s.external_bytes = 1
+    assert R.storage_bytes(s) == got
+
+
+def test_storage_bytes_and_external_fields_are_checked(L):
+    n = ctypes.c_uint64()
+    assert L.rc_tables_storage_bytes(None, ctypes.byref(n)) == -1
+    s = R.default_spec(8)
+    assert L.rc_tables_storage_bytes(ctypes.byref(s), None) == -1
+    bad = R.default_spec(8)
+    bad.cool.n[0] = 1
+    assert L.rc_tables_storage_bytes(ctypes.byref(bad), ctypes.byref(n)) == -1
+    # a size without storage is an inconsistent spec: refused before any device call
+    h = ctypes.c_void_p()
+    s.external_bytes = 1 << 20
+    assert L.rc_build_tables(ctypes.byref(s), None, ctypes.byref(h)) == -1
+    assert not h.value
+    resid = np.zeros(4 * 512, dtype=np.float32)
+    co = np.zeros(16)
+    assert L.rc_tables_import(ctypes.byref(s), resid.ctypes.data_as(ctypes.c_void_p),
+                              co.ctypes.data_as(ctypes.c_void_p), None, ctypes.byref(h)) == -1
+    d = R.default_spec(8)
+    assert d.external_storage is None and d.external_bytes == 0
