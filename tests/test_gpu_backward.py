@@ -64,6 +64,54 @@ def test_backward_matches_oracle(dev, imported):
         assert np.max(np.abs(got - want)) <= 1e-8 * np.max(np.abs(want)), name
 
 
+def test_backward_full_size_sampled(dev, imported):
+    """The adjoint at full size (2^21 iid cells, 64^3 tables) with cotangents
+    on a seeded sample of 4096 cells and zero elsewhere: every cell goes
+    through the adjoint kernel and the table-gradient records, but a cell with
+    zero cotangent adds exactly nothing, so the table gradients are the
+    oracle's over the sample alone (the table gradient is a sum over cells);
+    the sample's input gradients match the oracle's, the other cells' are 0."""
+    gt, ts = imported
+    cells = W.workload(3)
+    n = cells["n_e"].size
+    assert n == 2 ** 21
+    st = {k: to_dev(cells[k], dev) for k in W.FIELDS}
+    fwd = R.cool_step(gt, st, DT)
+    rng = np.random.default_rng(21)
+    idx = np.sort(rng.choice(n, size=4096, replace=False))
+    cot_s = {k: rng.normal(size=idx.size) for k in ("T_e_new", "T_i_new", "Q_rad", "Q_cc")}
+    cot = {}
+    for k, v in cot_s.items():
+        full = np.zeros(n)
+        full[idx] = v
+        cot[k] = to_dev(full, dev)
+    _, nv = gt.info()
+    tg = torch.zeros(nv, dtype=torch.float64, device=dev)
+    g = R.cool_step_backward(gt, st, DT, fwd, cot, table_grad=tg)
+    sample = {f: cells[f][idx] for f in W.FIELDS}
+    ref_fwd = S.step_be(ts, *[sample[f] for f in W.FIELDS], DT)
+    out = {k: v.cpu().numpy()[idx] for k, v in fwd.items()}
+    for k in ("T_e_new", "T_i_new"):
+        assert np.max(np.abs(out[k] - ref_fwd[k]) / ref_fwd[k]) < 1e-9, k
+    ref = Gd.vjp_step_be(ts, sample, ref_fwd, DT, cot_s["T_e_new"], cot_s["T_i_new"], cot_s["Q_rad"],
+                         cot_s["Q_cc"])
+    mag = (np.abs(cot_s["T_e_new"] * out["T_e_new"]) + np.abs(cot_s["T_i_new"] * out["T_i_new"])
+           + np.abs(cot_s["Q_rad"] * out["Q_rad"]) + np.abs(cot_s["Q_cc"] * out["Q_cc"]))
+    rest = np.ones(n, dtype=bool)
+    rest[idx] = False
+    for f in W.FIELDS:
+        gf = g[f].cpu().numpy()
+        err = np.abs(gf[idx] - ref[f]) * sample[f]
+        assert np.all(err <= 1e-8 * np.abs(ref[f] * sample[f]) + 1e-11 * mag), f
+        assert not np.any(gf[rest]), f
+    tgn = tg.cpu().numpy()
+    vc = 64 ** 3
+    for k, name in enumerate(T.TABLE_NAMES):
+        want = ref["tables"][name].ravel()
+        got = tgn[k * vc:(k + 1) * vc]
+        assert np.max(np.abs(got - want)) <= 1e-8 * np.max(np.abs(want)), name
+
+
 def test_autograd_radiated_energy(dev, imported):
     """dE/d(inputs, table entries) of the total radiated energy through
     torch.autograd, against the oracle: E = sum c (T_e + T_i - T_e' - T_i')."""
