@@ -404,9 +404,11 @@ typedef struct {
  * per-cell arrays (length n) are overwritten; NULL = not written.  tables
  * (n_values doubles, laid out as the residuals of rc_tables_import: gradient
  * with respect to each table's log2 node values) is accumulated (+=); the
- * per-cell contributions are grouped by table cell with integer atomics, so
- * their summation order, and the last bits of the values, vary from run to
- * run; NULL = not computed. */
+ * per-cell contributions are grouped by buckets of table cells and summed
+ * with atomic adds in local memory (and, for table cells crowded with more
+ * contributions than one workgroup takes, in device memory), so their
+ * summation order, and the last bits of the values, vary from run to run;
+ * NULL = not computed. */
 typedef struct {
   double* n_e;
   double* T_e;
@@ -429,8 +431,9 @@ typedef struct {
  * through the cell-blocked copy (a call that finds it missing builds it:
  * allocates and synchronizes its stream), GLOBAL and LDS the node layout;
  * every variant gives the same gradients.  With table
- * gradients the call keeps device scratch in the table handle: two records
- * per cell (about 160 bytes per cell) plus 24 doubles per table cell, allocated
+ * gradients the call keeps device scratch in the table handle: per-point
+ * records, their keys and their bucket placement (about 200 bytes per cell)
+ * plus 24 doubles per table cell, allocated
  * (hipMalloc) on the first call and whenever n grows past what it holds;
  * backward calls with table gradients that overlap on one table handle must
  * therefore use the same stream.  Asynchronous on stream. */

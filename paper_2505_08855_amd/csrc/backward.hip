@@ -3,13 +3,12 @@
 // One thread per cell: recompute the interpolant pieces at the forward
 // solution and at the input state, solve the transposed 2x2 system and write
 // the five input gradients (coalesced).  Table-entry gradients, when asked
-// for, take no floating-point atomics: every cell writes one record per
-// evaluation point (its table cell, coefficients and fractional coordinates),
-// a counting sort groups the records by table cell (integer atomics on the
-// counts and placement cursors, aggregated per wavefront), one thread per
-// table cell (one workgroup for a crowded one) adds up its records' corner
-// contributions into cell-blocked scratch, and a last pass folds the cells
-// onto the table nodes.
+// for, take no per-cell floating-point atomics in global memory: every cell
+// writes one record per evaluation point (its table cell, coefficients and
+// fractional coordinates); the records are grouped by bucket of consecutive
+// table cells (LDS histograms, a scan, LDS cursors), each bucket's corner
+// contributions are summed in LDS, and a last pass folds the cell-blocked
+// sums onto the table nodes.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -29,9 +28,9 @@ struct BwdArgs {
   const uint8_t* status;
   const double *g_x, *g_z, *g_qr, *g_qc;
   double *o_n, *o_Te, *o_Ti, *o_B, *o_H, *o_tab;
-  double* g_cool_cells;   // scratch, cell-blocked: {brem, synch * eta} per corner of each cooling cell
-  double* g_coul_cells;   // scratch, cell-blocked: one value per corner of each Coulomb cell
-  unsigned *key_cool, *key_coul, *cnt_cool, *cnt_coul;   // gradient records (see RecordScatter)
+  double* g_cool_cells;   // scratch, per cooling cell and corner k: brem at plane 2k, synch * eta at 2k + 1
+  double* g_coul_cells;   // scratch, per Coulomb cell and corner k at plane k (planes of one value per cell)
+  unsigned *key_cool, *key_coul;   // gradient records (see RecordScatter)
   double *rec_cool, *rec_coul;
   int c1, c2, k1, k2;
   long vc;
@@ -47,54 +46,28 @@ struct NoScatter {
 };
 
 // Table-gradient records: the adjoint writes, per cell and evaluation point,
-// the table cell it fell in, its coefficients and fractional coordinates
-// (cooling: cb, cse, t0, t1, t2; Coulomb: cc, t0, t1, t2) and counts the
-// records of each table cell; a counting sort by table cell then lets one
-// thread per table cell add up its records' corner contributions without
-// atomics on the gradients.  Record r = 2 i + p of cell i and point p; its key
-// is ~0u when the point contributes nothing.
-// Add 1 to cnt[key] for every active lane.  Neighbouring cells of coherent
-// inputs share table cells, and one atomic per lane on one counter serializes;
-// so the first kPeel distinct keys among the active lanes of the wavefront
-// take one atomic each, and the lanes left (independent inputs) one each.
-// The peel loop is uniform over the active lanes.
-constexpr int kPeel = 4;
-
-__device__ inline void wave_count(unsigned* cnt, unsigned key) {
-  const int lane = (int)(threadIdx.x & 63);
-  uint64_t todo = __ballot(1);
-  for (int it = 0; it < kPeel && todo; ++it) {
-    const int leader = __ffsll((unsigned long long)todo) - 1;
-    const unsigned lk = __shfl(key, leader);
-    const uint64_t same = __ballot(key == lk) & todo;
-    if (lane == leader) atomicAdd(cnt + lk, (unsigned)__popcll(same));
-    todo &= ~same;
-  }
-  if ((todo >> lane) & 1ull) atomicAdd(cnt + key, 1u);
-}
-
+// the table cell it fell in (its key), its coefficients and fractional
+// coordinates (cooling: cb, cse, t0, t1, t2; Coulomb: cc, t0, t1, t2).
+// Record r = 2 i + p of cell i and point p; its key is ~0u when the point
+// contributes nothing.
 struct RecordScatter {
   enum { kRecords = 1 };
   unsigned* key_cool;
   double* rec_cool;
-  unsigned* cnt_cool;
   unsigned* key_coul;
   double* rec_coul;
-  unsigned* cnt_coul;
   long r0;
   __device__ void cool_rec(int p, long cell, double cb, double cse, const double* t) const {
     const long r = r0 + p;
     double* q = rec_cool + r * 5;
     q[0] = cb; q[1] = cse; q[2] = t[0]; q[3] = t[1]; q[4] = t[2];
     key_cool[r] = (unsigned)cell;
-    wave_count(cnt_cool, (unsigned)cell);
   }
   __device__ void coul_rec(int p, long cell, double cc, const double* t) const {
     const long r = r0 + p;
     double* q = rec_coul + r * 4;
     q[0] = cc; q[1] = t[0]; q[2] = t[1]; q[3] = t[2];
     key_coul[r] = (unsigned)cell;
-    wave_count(cnt_coul, (unsigned)cell);
   }
 };
 
@@ -105,7 +78,7 @@ __global__ __launch_bounds__(256, 2) void k_backward(Tab tab, StepParams P, BwdA
   using Scatter = typename std::conditional<CELLS, RecordScatter, NoScatter>::type;
   Scatter sc;
   if constexpr (CELLS) {
-    sc = RecordScatter{a.key_cool, a.rec_cool, a.cnt_cool, a.key_coul, a.rec_coul, a.cnt_coul, 2 * i};
+    sc = RecordScatter{a.key_cool, a.rec_cool, a.key_coul, a.rec_coul, 2 * i};
     a.key_cool[2 * i] = a.key_cool[2 * i + 1] = ~0u;
     a.key_coul[2 * i] = a.key_coul[2 * i + 1] = ~0u;
   }
@@ -122,10 +95,6 @@ __global__ __launch_bounds__(256, 2) void k_backward(Tab tab, StepParams P, BwdA
   if (a.o_Ti) a.o_Ti[i] = g.T_i;
   if (a.o_B) a.o_B[i] = g.B;
   if (a.o_H) a.o_H[i] = g.H;
-}
-
-__global__ void k_zero_u32(unsigned* p, long n) {
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0u;
 }
 
 // exclusive scan of 1024-element chunks (one workgroup each); chunk totals to sums
@@ -150,114 +119,15 @@ __global__ void k_scan_add(unsigned* out, const unsigned* offs, long n) {
     out[i] += offs[i / 1024];
 }
 
-// place record indices by table cell (cursor starts as the exclusive scan);
-// lanes of a wavefront with the same key take consecutive places from one atomic
-__global__ __launch_bounds__(256) void k_order(const unsigned* key, unsigned* cursor, unsigned* order, long nrec) {
-  const int lane = (int)(threadIdx.x & 63);
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  // whole wavefronts step through the records so that every ballot is uniform
-  const long stride = (long)gridDim.x * blockDim.x;
-  for (long base = blockIdx.x * (long)blockDim.x; base < nrec; base += stride) {
-    const long r = base + threadIdx.x;
-    const unsigned k = r < nrec ? key[r] : ~0u;
-    uint64_t todo = __ballot(k != ~0u);
-    for (int it = 0; it < kPeel && todo; ++it) {
-      const int leader = __ffsll((unsigned long long)todo) - 1;
-      const unsigned lk = __shfl(k, leader);
-      const uint64_t same = __ballot(k == lk) & todo;
-      unsigned pos0 = 0;
-      if (lane == leader) pos0 = atomicAdd(cursor + lk, (unsigned)__popcll(same));
-      pos0 = __shfl(pos0, leader);
-      if ((same >> lane) & 1ull) order[pos0 + __popcll(same & below)] = (unsigned)r;
-      todo &= ~same;
-    }
-    if ((todo >> lane) & 1ull) order[atomicAdd(cursor + k, 1u)] = (unsigned)r;
-  }
-}
-
-// table cells with more records than this are summed by k_gather_heavy
-constexpr unsigned kHeavy = 128;
-
-// one thread per table cell: the corner contributions of its records, written
-// to the cell-blocked gradient scratch (zero for a cell without records, and
-// for a heavy cell, which k_gather_heavy then adds to)
-template <bool COOL>
-__global__ void k_gather_records(const unsigned* start, const unsigned* cnt, const unsigned* order,
-                                 const double* rec, double* cells, long ncell, unsigned* heavy, unsigned* nheavy) {
-  for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < ncell; c += (long)gridDim.x * blockDim.x) {
-    double acc0[8], acc1[8];
-    for (int k = 0; k < 8; ++k) acc0[k] = acc1[k] = 0.0;
-    const bool is_heavy = cnt[c] > kHeavy;
-    if (is_heavy) heavy[atomicAdd(nheavy, 1u)] = (unsigned)c;
-    const unsigned b = start[c], m = is_heavy ? 0u : cnt[c];   // heavy cells: k_gather_heavy
-    for (unsigned j = 0; j < m; ++j) {
-      const double* q = rec + (long)order[b + j] * (COOL ? 5 : 4);
-      const double c0 = q[0], c1 = COOL ? q[1] : 0.0;
-      const double t0 = q[COOL ? 2 : 1], t1 = q[COOL ? 3 : 2], t2 = q[COOL ? 4 : 3];
-      for (int k = 0; k < 8; ++k) {
-        const double w = ((k >> 2) ? t0 : 1.0 - t0) * (((k >> 1) & 1) ? t1 : 1.0 - t1) * ((k & 1) ? t2 : 1.0 - t2);
-        acc0[k] += c0 * w;
-        if (COOL) acc1[k] += c1 * w;
-      }
-    }
-    if (COOL) {
-      for (int k = 0; k < 8; ++k) {
-        cells[c * 16 + 2 * k] = acc0[k];
-        cells[c * 16 + 2 * k + 1] = acc1[k];
-      }
-    } else {
-      for (int k = 0; k < 8; ++k) cells[c * 8 + k] = acc0[k];
-    }
-  }
-}
-
-// heavy table cells (coherent inputs put many cells into one table cell):
-// one workgroup per heavy cell, its threads striding over the cell's records,
-// then a workgroup reduction and plain stores (no floating-point atomics)
-template <bool COOL>
-__global__ __launch_bounds__(256) void k_gather_heavy(const unsigned* start, const unsigned* cnt, const unsigned* order,
-                                                      const double* rec, double* cells, const unsigned* heavy,
-                                                      const unsigned* nheavy) {
-  constexpr int V = COOL ? 16 : 8;
-  __shared__ double red[V][256];
-  const unsigned nh = *nheavy;
-  for (unsigned h = blockIdx.x; h < nh; h += gridDim.x) {
-    const unsigned c = heavy[h];
-    const unsigned b = start[c], m = cnt[c];
-    double acc[V];
-    for (int v = 0; v < V; ++v) acc[v] = 0.0;
-    for (unsigned j = threadIdx.x; j < m; j += blockDim.x) {
-      const double* q = rec + (long)order[b + j] * (COOL ? 5 : 4);
-      const double c0 = q[0], c1 = COOL ? q[1] : 0.0;
-      const double t0 = q[COOL ? 2 : 1], t1 = q[COOL ? 3 : 2], t2 = q[COOL ? 4 : 3];
-      for (int k = 0; k < 8; ++k) {
-        const double w = ((k >> 2) ? t0 : 1.0 - t0) * (((k >> 1) & 1) ? t1 : 1.0 - t1) * ((k & 1) ? t2 : 1.0 - t2);
-        if (COOL) {
-          acc[2 * k] += c0 * w;
-          acc[2 * k + 1] += c1 * w;
-        } else {
-          acc[k] += c0 * w;
-        }
-      }
-    }
-    for (int v = 0; v < V; ++v) red[v][threadIdx.x] = acc[v];
-    __syncthreads();
-    for (int d = 128; d > 0; d >>= 1) {
-      if ((int)threadIdx.x < d)
-        for (int v = 0; v < V; ++v) red[v][threadIdx.x] += red[v][threadIdx.x + d];
-      __syncthreads();
-    }
-    if ((int)threadIdx.x < V) cells[(long)c * V + threadIdx.x] = red[threadIdx.x][0];
-    __syncthreads();
-  }
-}
-
-// fold cell-blocked gradients onto the nodes: node (i0, i1, i2) is corner
+// fold the per-cell gradients onto the nodes: node (i0, i1, i2) is corner
 // (a, b, m) of cell (i0 - a, i1 - b, i2 - m) wherever that cell exists; the
-// synch * eta gradient goes to both tables' slots
+// synch * eta gradient goes to both tables' slots.  The cell gradients are
+// stored corner-plane by corner-plane (plane p holds one value per table
+// cell), so consecutive nodes read consecutive cells of each plane.
 __global__ void k_finish_cells(double* g_tab, const double* cool_cells, const double* coul_cells, int n0, int n1,
                                int n2, int m0, int m1, int m2) {
   const long vc = (long)n0 * n1 * n2, vk = (long)m0 * m1 * m2;
+  const long mc = (long)(n0 - 1) * (n1 - 1) * (n2 - 1), mk = (long)(m0 - 1) * (m1 - 1) * (m2 - 1);
   for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j < vc + vk; j += (long)gridDim.x * blockDim.x) {
     const bool cl = j < vc;
     const long v = cl ? j : j - vc;
@@ -270,10 +140,10 @@ __global__ void k_finish_cells(double* g_tab, const double* cool_cells, const do
       if (c0 < 0 || c1 < 0 || c2 < 0 || c0 > d0 - 2 || c1 > d1 - 2 || c2 > d2 - 2) continue;
       const long cell = ((long)c0 * (d1 - 1) + c1) * (d2 - 1) + c2;
       if (cl) {
-        s0 += cool_cells[cell * 16 + 2 * k];
-        s1 += cool_cells[cell * 16 + 2 * k + 1];
+        s0 += cool_cells[(2 * k) * mc + cell];
+        s1 += cool_cells[(2 * k + 1) * mc + cell];
       } else {
-        s0 += coul_cells[cell * 8 + k];
+        s0 += coul_cells[k * mk + cell];
       }
     }
     if (cl) {
@@ -295,6 +165,182 @@ void scan_counts(const unsigned* in, unsigned* out, long m, unsigned* tmp, hipSt
     scan_counts(tmp, tmp, nb, tmp + nb, hs);
     hipLaunchKernelGGL(k_scan_add, dim3(4096), dim3(256), 0, hs, out, (const unsigned*)tmp, m);
   }
+}
+
+// ------------------------------------------------------------------ bucketed table gradients
+//
+// The records of one table kind are grouped by bucket: cpb consecutive table
+// cells, a whole number of LDS windows of kW cells (a window's cell-blocked
+// gradients fill 32 KiB), with as few windows per bucket as keep the bucket
+// count within kMaxBuckets (one window per bucket up to about 3 million table
+// cells).  A count pass builds, per workgroup of kPlaceChunk records, an LDS
+// histogram of their buckets and writes it as one column of a bucket-major
+// count matrix; an exclusive scan of the matrix gives every (bucket,
+// workgroup) pair its first position; a placement pass recounts with LDS
+// cursors seeded from the scan and writes each record's index and its table
+// cell inside the bucket there (no global atomics).  Then one workgroup per
+// slice of at most kSlice records of a bucket adds, window by window, the
+// slice's corner contributions into LDS (FP64 atomic adds in LDS) and writes
+// the window out: plain stores when the bucket has one slice, global FP64
+// atomic adds of the nonzero entries when it has several (crowded table cells
+// of coherent inputs; the gradient scratch is zeroed first).  Sums in LDS and
+// across slices are taken in a run-dependent order.
+
+constexpr int kWindowBytes = 32768;          // a window's cell-blocked sums (plus one pad double per cell)
+constexpr long kMaxBuckets = 12288;          // LDS histogram of 48 KiB
+constexpr long kPlaceChunk = 16384;          // records per workgroup of the count and placement passes
+constexpr unsigned kSlice = 16384;           // records per workgroup of the accumulation
+constexpr int kUnroll = 8;                   // keys in flight per thread (count, placement)
+constexpr int kAccUnroll = 4;                // records in flight per thread (accumulation)
+
+template <bool COOL> constexpr int kV = COOL ? 16 : 8;                   // doubles per table cell
+template <bool COOL> constexpr int kW = kWindowBytes / (kV<COOL> * 8);   // table cells per LDS window
+
+// table cells per bucket for m table cells: the fewest whole windows that
+// keep the number of buckets within kMaxBuckets
+template <bool COOL>
+long cells_per_bucket(long m) {
+  const long per = kW<COOL> * kMaxBuckets;
+  return kW<COOL> * ((m + per - 1) / per);
+}
+
+__global__ __launch_bounds__(256) void k_bucket_count(const unsigned* key, long nrec, unsigned cpb, int nb,
+                                                      unsigned* hist) {
+  extern __shared__ unsigned lh[];
+  const int tid = (int)threadIdx.x;
+  const long g = blockIdx.x, G = gridDim.x;
+  for (int b = tid; b < nb; b += blockDim.x) lh[b] = 0u;
+  __syncthreads();
+  const long r1 = nrec < (g + 1) * kPlaceChunk ? nrec : (g + 1) * kPlaceChunk;
+  // kUnroll keys in flight per thread
+  for (long rb = g * kPlaceChunk + tid; rb < r1; rb += kUnroll * (long)blockDim.x) {
+    unsigned k[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) k[u] = rb + u * (long)blockDim.x < r1 ? key[rb + u * (long)blockDim.x] : ~0u;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (k[u] != ~0u) atomicAdd(&lh[k[u] / cpb], 1u);
+  }
+  __syncthreads();
+  for (int b = tid; b < nb; b += blockDim.x) hist[(long)b * G + g] = lh[b];
+}
+
+__global__ __launch_bounds__(256) void k_bucket_place(const unsigned* key, long nrec, unsigned cpb, int nb,
+                                                      const unsigned* offs, uint2* order) {
+  extern __shared__ unsigned lc[];
+  const int tid = (int)threadIdx.x;
+  const long g = blockIdx.x, G = gridDim.x;
+  for (int b = tid; b < nb; b += blockDim.x) lc[b] = offs[(long)b * G + g];
+  __syncthreads();
+  const long r1 = nrec < (g + 1) * kPlaceChunk ? nrec : (g + 1) * kPlaceChunk;
+  for (long rb = g * kPlaceChunk + tid; rb < r1; rb += kUnroll * (long)blockDim.x) {
+    unsigned k[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) k[u] = rb + u * (long)blockDim.x < r1 ? key[rb + u * (long)blockDim.x] : ~0u;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (k[u] == ~0u) continue;
+      const unsigned b = k[u] / cpb;
+      order[atomicAdd(&lc[b], 1u)] = make_uint2((unsigned)(rb + u * (long)blockDim.x), k[u] - b * cpb);
+    }
+  }
+}
+
+// slices per bucket; the records of bucket b are [offs[b G], offs[(b + 1) G])
+// (the last bucket ends at the number of records placed)
+__global__ void k_bucket_slices(const unsigned* hist, const unsigned* offs, long G, int nb, unsigned* ns) {
+  const unsigned total = offs[(long)nb * G - 1] + hist[(long)nb * G - 1];
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+    const unsigned lo = offs[(long)b * G], hi = b + 1 < nb ? offs[(long)(b + 1) * G] : total;
+    ns[b] = (hi - lo + kSlice - 1) / kSlice;
+  }
+}
+
+template <bool COOL>
+__global__ __launch_bounds__(256) void k_bucket_accum(const uint2* order, const double* rec, const unsigned* hist,
+                                                      const unsigned* offs, long G, unsigned cpb, int nb,
+                                                      const unsigned* ns, const unsigned* sstart, double* cells,
+                                                      long m) {
+  // a window's cell-blocked sums in LDS, V + 1 doubles per cell: the odd
+  // stride spreads the lanes' random cells over the LDS banks (with a stride
+  // of V doubles every cell starts in the same two banks)
+  constexpr int V = kV<COOL>, W = kW<COOL>, RW = COOL ? 5 : 4, VP = V + 1;
+  __shared__ double acc[W * VP];
+  const unsigned w = blockIdx.x;
+  if (w >= sstart[nb - 1] + ns[nb - 1]) return;           // past the last slice (uniform)
+  // the slice's bucket: the last b with sstart[b] <= w (buckets without
+  // records have no slice and share their successor's start)
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sstart[mid] <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  const int b = lo;
+  const int tid = (int)threadIdx.x;
+  const unsigned total = offs[(long)nb * G - 1] + hist[(long)nb * G - 1];
+  const unsigned bend = b + 1 < nb ? offs[(long)(b + 1) * G] : total;
+  const unsigned j0 = offs[(long)b * G] + (w - sstart[b]) * kSlice;
+  const unsigned j1 = bend - j0 < kSlice ? bend : j0 + kSlice;
+  const bool single = ns[b] == 1;
+  for (unsigned w0 = 0; w0 < cpb; w0 += W) {
+    const long first = (long)b * cpb + w0;                 // first table cell of the window
+    if (first >= m) break;                                 // uniform
+    for (int i = tid; i < W * VP; i += blockDim.x) acc[i] = 0.0;
+    __syncthreads();
+    // kAccUnroll records in flight per thread: their placements, then their records
+    for (unsigned jb = j0 + tid; jb < j1; jb += kAccUnroll * blockDim.x) {
+      unsigned lc[kAccUnroll], ri[kAccUnroll];
+      double q[kAccUnroll][RW];
+#pragma unroll
+      for (int u = 0; u < kAccUnroll; ++u) {
+        const unsigned j = jb + u * blockDim.x;
+        const uint2 o = j < j1 ? order[j] : make_uint2(0u, ~0u);
+        ri[u] = o.x;
+        lc[u] = o.y - w0;                                 // ~0u: past the slice
+        if (o.y == ~0u || lc[u] >= (unsigned)W) lc[u] = ~0u;   // or another window's cell
+      }
+#pragma unroll
+      for (int u = 0; u < kAccUnroll; ++u)
+        if (lc[u] != ~0u) {
+          const double* r = rec + (long)ri[u] * RW;
+#pragma unroll
+          for (int v = 0; v < RW; ++v) q[u][v] = r[v];
+        }
+#pragma unroll
+      for (int u = 0; u < kAccUnroll; ++u) {
+        if (lc[u] == ~0u) continue;
+        const double c0 = q[u][0], c1 = COOL ? q[u][1] : 0.0;
+        const double t0 = q[u][COOL ? 2 : 1], t1 = q[u][COOL ? 3 : 2], t2 = q[u][COOL ? 4 : 3];
+        double* a = acc + lc[u] * VP;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const double wk = ((k >> 2) ? t0 : 1.0 - t0) * (((k >> 1) & 1) ? t1 : 1.0 - t1) * ((k & 1) ? t2 : 1.0 - t2);
+          if (COOL) {
+            atomicAdd(a + 2 * k, c0 * wk);
+            atomicAdd(a + 2 * k + 1, c1 * wk);
+          } else {
+            atomicAdd(a + k, c0 * wk);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // out to the corner planes: the window's cells are consecutive in each plane
+    const long n_here = m - first < W ? m - first : W;
+    for (long i = tid; i < n_here * V; i += blockDim.x) {
+      const long p = i / n_here, c = i - p * n_here;
+      const double v = acc[c * VP + p];
+      double* out = cells + p * m + first + c;
+      if (single) *out = v;
+      else if (v != 0.0) atomicAdd(out, v);
+    }
+    __syncthreads();                                       // before the next window clears acc
+  }
+}
+
+__global__ void k_zero_f64(double* p, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0.0;
 }
 
 }  // namespace rc
@@ -356,19 +402,26 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
     return with_tab(t, f);
   };
   a.g_cool_cells = a.g_coul_cells = nullptr;
-  a.key_cool = a.key_coul = a.cnt_cool = a.cnt_coul = nullptr;
+  a.key_cool = a.key_coul = nullptr;
   a.rec_cool = a.rec_coul = nullptr;
   const rc_axes &ca = t->spec.cool, &ka = t->spec.coul;
   const long mc = (long)(ca.n[0] - 1) * (ca.n[1] - 1) * (ca.n[2] - 1);   // table cells
   const long mk = (long)(ka.n[0] - 1) * (ka.n[1] - 1) * (ka.n[2] - 1);
   const long nrec = 2 * n;                                               // records per table kind
   if (nrec > 0xfffffffeLL) return set_error(RC_EINVAL, "rc_cool_step_backward: n too large for the gradient records");
-  // scratch: [cooling cells x 16][Coulomb cells x 8][cooling records x 5][Coulomb records x 4] doubles, then
-  // uint32: keys, orders (2 x nrec each), counts, starts, cursors (3 x (mc + mk)), scan sums
-  const long sc_c = 2 * ((mc + 1023) / 1024) + 2, sc_k = 2 * ((mk + 1023) / 1024) + 2;
-  const size_t dbl = sizeof(double) * (size_t)(16 * mc + 8 * mk + 9 * nrec);
-  const size_t u32 = sizeof(unsigned) * (size_t)(4 * nrec + 4 * (mc + mk) + sc_c + sc_k + 2);
   if (a.o_tab) {
+    // buckets of each kind (cells per bucket, bucket count), workgroups of the count and placement passes
+    const long cpb_c = cells_per_bucket<true>(mc), cpb_k = cells_per_bucket<false>(mk);
+    const long nbc = (mc + cpb_c - 1) / cpb_c, nbk = (mk + cpb_k - 1) / cpb_k;
+    const long Gr = (nrec + kPlaceChunk - 1) / kPlaceChunk;
+    // scratch: [cooling cells x 16][Coulomb cells x 8][cooling records x 5][Coulomb records x 4] doubles,
+    // then uint32: keys (2 x nrec), placed records (2 x nrec uint2), count matrices and their scans
+    // (2 x (nbc + nbk) x Gr), slices per bucket and their scans (2 x (nbc + nbk)), scan sums
+    const long mat = (nbc + nbk) * Gr;
+    const long tmpn = 2 * (((nbc > nbk ? nbc : nbk) * Gr + 1023) / 1024) + 2;   // the largest scan's sums
+    if (mat > 0x7fffffffL) return set_error(RC_EINVAL, "rc_cool_step_backward: n too large for the gradient buckets");
+    const size_t dbl = sizeof(double) * (size_t)(16 * mc + 8 * mk + 9 * nrec);
+    const size_t u32 = sizeof(unsigned) * (size_t)(2 * nrec + 4 * nrec + 2 * mat + 2 * (nbc + nbk) + tmpn);
     if (t->gscratch_bytes < dbl + u32) {
       if (t->d_gscratch) (void)hipFree(t->d_gscratch);
       t->d_gscratch = nullptr;
@@ -385,43 +438,45 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
     unsigned* u = (unsigned*)((char*)t->d_gscratch + dbl);
     a.key_cool = u;
     a.key_coul = u + nrec;
-    unsigned* order_cool = u + 2 * nrec;
-    unsigned* order_coul = u + 3 * nrec;
-    a.cnt_cool = u + 4 * nrec;
-    a.cnt_coul = a.cnt_cool + mc;
-    unsigned* start_cool = a.cnt_coul + mk;
-    unsigned* start_coul = start_cool + mc;
-    unsigned* cur_cool = start_coul + mk;
-    unsigned* cur_coul = cur_cool + mc;
-    unsigned* tmp_c = cur_coul + mk;
-    unsigned* tmp_k = tmp_c + sc_c;
-    unsigned* heavy_cool = tmp_k + sc_k;
-    unsigned* heavy_coul = heavy_cool + mc;
-    unsigned* nheavy = heavy_coul + mk;   // [cooling, Coulomb]
-    hipLaunchKernelGGL(k_zero_u32, dim3(4096), dim3(256), 0, hs, a.cnt_cool, mc + mk);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, hs, nheavy, 2L);
+    uint2* order_cool = (uint2*)(u + 2 * nrec);
+    uint2* order_coul = order_cool + nrec;
+    unsigned* hist_c = u + 6 * nrec;
+    unsigned* offs_c = hist_c + nbc * Gr;
+    unsigned* hist_k = offs_c + nbc * Gr;
+    unsigned* offs_k = hist_k + nbk * Gr;
+    unsigned* ns_c = offs_k + nbk * Gr;
+    unsigned* ss_c = ns_c + nbc;
+    unsigned* ns_k = ss_c + nbc;
+    unsigned* ss_k = ns_k + nbk;
+    unsigned* tmp = ss_k + nbk;
+    hipLaunchKernelGGL(k_zero_f64, dim3(4096), dim3(256), 0, hs, a.g_cool_cells, 16 * mc + 8 * mk);
     with_bwd_tab([&](auto tab) {
       hipLaunchKernelGGL((k_backward<decltype(tab), true>), dim3((unsigned)grid), dim3(block), 0, hs, tab, P, a, n);
       return 0;
     });
-    scan_counts(a.cnt_cool, start_cool, mc, tmp_c, hs);
-    scan_counts(a.cnt_coul, start_coul, mk, tmp_k, hs);
-    hipError_t ce = hipMemcpyAsync(cur_cool, start_cool, sizeof(unsigned) * (mc + mk), hipMemcpyDeviceToDevice, hs);
-    if (ce != hipSuccess) return hip_fail(ce, "rc_cool_step_backward: cursor copy");
-    hipLaunchKernelGGL(k_order, dim3(4096), dim3(256), 0, hs, (const unsigned*)a.key_cool, cur_cool, order_cool, nrec);
-    hipLaunchKernelGGL(k_order, dim3(4096), dim3(256), 0, hs, (const unsigned*)a.key_coul, cur_coul, order_coul, nrec);
-    hipLaunchKernelGGL(k_gather_records<true>, dim3(4096), dim3(256), 0, hs, (const unsigned*)start_cool,
-                       (const unsigned*)a.cnt_cool, (const unsigned*)order_cool, (const double*)a.rec_cool,
-                       a.g_cool_cells, mc, heavy_cool, nheavy);
-    hipLaunchKernelGGL(k_gather_records<false>, dim3(4096), dim3(256), 0, hs, (const unsigned*)start_coul,
-                       (const unsigned*)a.cnt_coul, (const unsigned*)order_coul, (const double*)a.rec_coul,
-                       a.g_coul_cells, mk, heavy_coul, nheavy + 1);
-    hipLaunchKernelGGL(k_gather_heavy<true>, dim3(1024), dim3(256), 0, hs, (const unsigned*)start_cool,
-                       (const unsigned*)a.cnt_cool, (const unsigned*)order_cool, (const double*)a.rec_cool,
-                       a.g_cool_cells, (const unsigned*)heavy_cool, (const unsigned*)nheavy);
-    hipLaunchKernelGGL(k_gather_heavy<false>, dim3(1024), dim3(256), 0, hs, (const unsigned*)start_coul,
-                       (const unsigned*)a.cnt_coul, (const unsigned*)order_coul, (const double*)a.rec_coul,
-                       a.g_coul_cells, (const unsigned*)heavy_coul, (const unsigned*)(nheavy + 1));
+    // per kind: bucket counts, their scan, placement, slices per bucket and their scan, accumulation
+    const auto group = [&](auto cool, const unsigned* key, const double* rec, long m, long cpb, long nb,
+                           unsigned* hist, unsigned* offs, uint2* order, unsigned* ns, unsigned* ss, double* cells) {
+      constexpr bool C = decltype(cool)::value;
+      const size_t lds = sizeof(unsigned) * (size_t)nb;
+      hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)Gr), dim3(256), lds, hs, key, nrec, (unsigned)cpb, (int)nb,
+                         hist);
+      scan_counts(hist, offs, nb * Gr, tmp, hs);
+      hipLaunchKernelGGL(k_bucket_place, dim3((unsigned)Gr), dim3(256), lds, hs, key, nrec, (unsigned)cpb, (int)nb,
+                         (const unsigned*)offs, order);
+      hipLaunchKernelGGL(k_bucket_slices, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, hs, (const unsigned*)hist,
+                         (const unsigned*)offs, Gr, (int)nb, ns);
+      scan_counts(ns, ss, nb, tmp, hs);
+      // at most one slice per bucket plus one per kSlice records
+      const unsigned slices = (unsigned)(nb + (nrec + kSlice - 1) / kSlice);
+      hipLaunchKernelGGL((k_bucket_accum<C>), dim3(slices), dim3(256), 0, hs, (const uint2*)order, rec,
+                         (const unsigned*)hist, (const unsigned*)offs, Gr, (unsigned)cpb, (int)nb,
+                         (const unsigned*)ns, (const unsigned*)ss, cells, m);
+    };
+    group(std::true_type{}, (const unsigned*)a.key_cool, (const double*)a.rec_cool, mc, cpb_c, nbc, hist_c, offs_c,
+          order_cool, ns_c, ss_c, a.g_cool_cells);
+    group(std::false_type{}, (const unsigned*)a.key_coul, (const double*)a.rec_coul, mk, cpb_k, nbk, hist_k, offs_k,
+          order_coul, ns_k, ss_k, a.g_coul_cells);
     hipLaunchKernelGGL(k_finish_cells, dim3(4096), dim3(256), 0, hs, a.o_tab, (const double*)a.g_cool_cells,
                        (const double*)a.g_coul_cells, ca.n[0], ca.n[1], ca.n[2], ka.n[0], ka.n[1], ka.n[2]);
   } else {

@@ -112,6 +112,81 @@ def test_backward_full_size_sampled(dev, imported):
         assert np.max(np.abs(got - want)) <= 1e-8 * np.max(np.abs(want)), name
 
 
+def test_table_gradients_of_one_crowded_table_cell(dev, imported):
+    """60,000 copies of one cell: every record of a kind falls into one table
+    cell, so its bucket is summed by several workgroups (a bounded number of
+    records each) whose partial sums meet in global atomic adds; the table
+    gradient is 60,000 times the oracle's for the single cell."""
+    gt, ts = imported
+    pool = W.workload(3, n=256)
+    k = int(np.flatnonzero((pool["T_e"] > 1e8) & (pool["T_e"] < 1e10) & (pool["T_i"] > 2 * pool["T_e"]))[0])
+    one = {f: pool[f][k:k + 1] for f in W.FIELDS}
+    n = 60000
+    st = {f: to_dev(np.repeat(one[f], n), dev) for f in W.FIELDS}
+    fwd = R.cool_step(gt, st, DT)
+    cot1 = {"T_e_new": np.array([0.7]), "T_i_new": np.array([-1.3]), "Q_rad": np.array([2e-9]),
+            "Q_cc": np.array([-5e-9])}
+    cot = {key: to_dev(np.repeat(v, n), dev) for key, v in cot1.items()}
+    _, nv = gt.info()
+    tg = torch.zeros(nv, dtype=torch.float64, device=dev)
+    R.cool_step_backward(gt, st, DT, fwd, cot, table_grad=tg)
+    ref_fwd = S.step_be(ts, *[one[f] for f in W.FIELDS], DT)
+    ref = Gd.vjp_step_be(ts, one, ref_fwd, DT, cot1["T_e_new"], cot1["T_i_new"], cot1["Q_rad"], cot1["Q_cc"])
+    tgn = tg.cpu().numpy()
+    vc = 64 ** 3
+    for j, name in enumerate(T.TABLE_NAMES):
+        want = n * ref["tables"][name].ravel()
+        assert np.count_nonzero(want) > 0, name
+        got = tgn[j * vc:(j + 1) * vc]
+        assert np.max(np.abs(got - want)) <= 1e-8 * np.max(np.abs(want)), name
+
+
+def test_table_gradients_of_large_tables_by_finite_differences(dev):
+    """Cooling tables of 256 x 128 x 128 nodes (4.1 million table cells: two
+    LDS windows per gradient bucket) at 20,000 iid cells: the table gradient
+    of L = sum(cot . outputs) along a random +-1 direction of the bremsstrahlung
+    and Coulomb residuals equals the central finite difference of L through
+    the forward step (the residuals perturbed by 3e-3 in log2, in FP32; the
+    per-cell step is piecewise smooth in the table values, so the two agree to
+    about 1e-3)."""
+    cool = ((256, 15.0, 29.0), (128, 5.95, 12.05), (128, -0.5, 10.5))
+    coul = ((64, 9.5, 20.5), (64, 5.95, 12.05), (64, 5.95, 14.05))
+    spec = R.spec_from_axes(cool, coul)
+    assert 255 * 127 * 127 > 256 * 12288
+    base = R.Tables.build(spec)
+    resid, coeffs = base.export()
+    cells = W.workload(3, n=20000)
+    st = {k: to_dev(cells[k], dev) for k in W.FIELDS}
+    rng = np.random.default_rng(8)
+    cot = {k: rng.normal(size=20000) for k in ("T_e_new", "T_i_new")}
+    cot.update({k: rng.normal(size=20000) * 1e-9 for k in ("Q_rad", "Q_cc")})
+    cot_d = {k: to_dev(v, dev) for k, v in cot.items()}
+
+    def loss(tables):
+        out = R.cool_step(tables, st, DT)
+        return sum(float(torch.sum(cot_d[k] * out[k])) for k in cot_d)
+
+    fwd = R.cool_step(base, st, DT)
+    _, nv = base.info()
+    tg = torch.zeros(nv, dtype=torch.float64, device=dev)
+    R.cool_step_backward(base, st, DT, fwd, cot_d, table_grad=tg)
+    g = tg.cpu().numpy()
+    vc = 256 * 128 * 128
+    delta = np.zeros(resid.size)
+    delta[:vc] = rng.choice([-1.0, 1.0], size=vc)
+    delta[3 * vc:] = rng.choice([-1.0, 1.0], size=resid.size - 3 * vc)
+    eps = 3e-3
+    rp = (resid + eps * delta).astype(np.float32)
+    rm = (resid - eps * delta).astype(np.float32)
+    tp, tm = R.Tables.from_storage(spec, rp, coeffs), R.Tables.from_storage(spec, rm, coeffs)
+    fd = (loss(tp) - loss(tm)) / (2 * eps)
+    # the perturbation the FP32 residuals actually received
+    lin = float(g @ (rp.astype(np.float64) - rm.astype(np.float64))) / (2 * eps)
+    assert abs(fd - lin) <= 1e-2 * abs(lin)
+    for t in (base, tp, tm):
+        t.destroy()
+
+
 def test_autograd_radiated_energy(dev, imported):
     """dE/d(inputs, table entries) of the total radiated energy through
     torch.autograd, against the oracle: E = sum c (T_e + T_i - T_e' - T_i')."""
