@@ -265,9 +265,10 @@ def _table_grad_gpu_vs_host(dev, gt, storage, cells, cot_seed):
 
 
 def test_table_gradient_records_coherent_and_ragged(dev, imported, storage):
-    """The record path on coherent cells (many cells per table cell: the
-    crowded-cell reduction), on independent cells with invalid ones and a
-    ragged count, and on successive calls of decreasing size (scratch reuse)."""
+    """The record path on coherent cells (many cells per table cell, added
+    concurrently into one cell's sums), on independent cells with invalid ones
+    and a ragged count, and on successive calls of decreasing size (scratch
+    reuse)."""
     gt, _ = imported
     _table_grad_gpu_vs_host(dev, gt, storage, W.sphere_cells(n_r=8, n_th=8, n_ph=256), 1)
     cells = W.workload(3, n=1001)

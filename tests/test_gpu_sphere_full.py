@@ -13,9 +13,9 @@ configuration of the default step.
   state (paper III.B, backward Euler).
 
 And the adjoint on coherent cells: patches of the profile put hundreds of
-cells into one table cell, so the table gradients go through the crowded-cell
-reduction; they are compared with the oracle's implicit-function-theorem
-gradient (not with the library's host code)."""
+cells into one table cell, so many contributions meet in one table cell's
+sums; the table gradients are compared with the oracle's
+implicit-function-theorem gradient (not with the library's host code)."""
 import numpy as np
 import pytest
 
@@ -104,8 +104,8 @@ def cells_per_cooling_cell(spec, cells, T_e):
 
 def test_adjoint_coherent_cells_against_oracle(dev, spec64, tables64):
     """Table and input gradients of the adjoint on coherent cells (table cells
-    holding more than 128 records: the workgroup reduction), against the
-    oracle's adjoint on identical table data."""
+    holding hundreds of records, added concurrently into one cell's sums),
+    against the oracle's adjoint on identical table data."""
     cells = W.sphere_cells(n_r=8, n_th=8, n_ph=256)
     n = cells["n_e"].size
     resid, coeffs, stored = storage_of(tables64)
@@ -117,8 +117,8 @@ def test_adjoint_coherent_cells_against_oracle(dev, spec64, tables64):
     ref_fwd = S.step_be(ts, *[cells[f] for f in W.FIELDS], DT)
     for k in ("T_e_new", "T_i_new"):
         assert np.max(rel_err(out[k], ref_fwd[k])) < 1e-9, k
-    # the crowded-cell path is taken: some table cell holds more than 128 of
-    # these cells, at the input state and at the updated one
+    # crowded table cells: some table cell holds more than 128 of these
+    # cells, at the input state and at the updated one
     assert cells_per_cooling_cell(spec64, cells, cells["T_e"]).max() > 128
     assert cells_per_cooling_cell(spec64, cells, out["T_e_new"]).max() > 128
     rng = np.random.default_rng(11)
