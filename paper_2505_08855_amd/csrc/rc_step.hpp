@@ -444,8 +444,12 @@ struct CellSolver {
   //      ln(dt q) + p d = ln(A (1 - e^d) + R0),  d = s' - s,
   //    A = c T_e (1 + dz/dx), R0 = c (T_i - z).  A heating cell (G < 0): the
   //    electrons' gain against a power law in x of the ion transfer (below).
-  //    Solved in single precision: it is only a proposal, and the safeguards
-  //    of the driver still apply.
+  //    Solved in single precision by kHeatSteps / kCoolSteps Newton steps on
+  //    the model from the Newton step of G: it is only a proposal, and the
+  //    safeguards of the driver still apply.  (A host count over 262,144 iid
+  //    cells and over the spherical profile: 5 and 4 model steps give the same
+  //    round counts as 1 and 2, so the model's own root need not be reached.)
+  static constexpr int kHeatSteps = 1, kCoolSteps = 2;
   RC_HD double outer(double s, double x, bool on, int mode, double* z, double* dG, double* q_out,
                      double* K_first, double* dzdx_out, double* ds3) {
     const double lx = s * (1.0 / kLn10);
@@ -489,7 +493,7 @@ struct CellSolver {
       const float p = q > 0.0 ? (float)fdiv_sp(dq, q) : 0.0f;
       const float b0 = (float)(-c * x * dzdx * iN0);
       float u = (float)fdiv_sp(-G, *dG * kLn2);
-      for (int k = 0; k < 5; ++k) {
+      for (int k = 0; k < kHeatSteps; ++k) {
         const float e = fexp2_sp(u), eq = fexp2_sp(p * u);
         const float Pn = a * (e - 1.0f) + r * eq;
         const float un = u - (flog2_sp(Pn) - b0 * u) * frcp_sp((a * e + p * r * eq) * frcp_sp(Pn) - b0);
@@ -504,7 +508,7 @@ struct CellSolver {
       const float L = flog2_sp((float)(dt * q * icx));
       const float r0 = (float)(c * (T_i - *z) * icx);
       float u = (float)fdiv_sp(-G, *dG * kLn2);
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < kCoolSteps; ++k) {
         const float e = fexp2_sp(u);
         const float R = (1.0f - e) + r0;
         const float un = u - (L + p * u - flog2_sp(R)) * frcp_sp(p + e * frcp_sp(R));
