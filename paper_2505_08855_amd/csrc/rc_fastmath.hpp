@@ -13,7 +13,7 @@
 //   exp2: y = k + f with k = rint(y), |f| <= 1/2; 2^f by its Taylor series in
 //         f (coefficients (ln 2)^j / j!, j <= 13; first omitted term < 2^-57).
 //   exp:  s = k ln 2 + r (Cody-Waite: k ln2_head exact), |r| <= 0.347,
-//         e^r by its Taylor series to r^13 / 13!.
+//         e^r by its Taylor series to r^13 / 13!, scaled by 2^k.
 //   log1p: u = 1 + v, log1p(v) = ln(u) v / (u - 1) (Goldberg's correction
 //         for the rounding of 1 + v; exact when u == 1).
 //
@@ -175,9 +175,13 @@ RC_HD double fexp2(double y) {
   return ldexp(p, (int)k);
 }
 
-// e^s; arguments outside |s| < 700 (including inf and NaN) take the library path
+// e^s.  The reduction reaches the whole double range: k up to 1024 (s below
+// ln DBL_MAX = 709.78 gives p 2^1024 < DBL_MAX) and the scaling by 2^k rounds
+// gradual underflow; beyond |s| = 746 e^s is +inf or 0, and inf and NaN go
+// the same way (no library fallback: its constants would stay live in
+// registers across the solver's loops)
 RC_HD double fexp(double s) {
-  if (!(fabs(s) < 700.0)) return exp(s);
+  if (!(fabs(s) < 746.0)) return s > 0.0 ? __builtin_inf() : (s < 0.0 ? 0.0 : s);
   const double k = rint(s * kLog2E);
   const double r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, s));
   double p = 1.0 / 6227020800.0;      // 1 / 13!

@@ -566,14 +566,14 @@ struct CellSolver {
       const bool on0 = (ns.flags & F_ON) != 0;
       if (ns.G > 0.0) {
         ns.hi = ns.s;
-        ns.lo = log(fmin(T_i, T_floor));
+        ns.lo = flog(fmin(T_i, T_floor));
         if (on0) ns.flags |= F_FLOOR_PENDING;
         else ns.flags |= F_LO_KNOWN;          // below the floor G(T_i) < 0 is guaranteed
         propose = true;
       } else {
         ns.flags |= F_HEATING | F_LO_KNOWN;
         ns.lo = ns.s;
-        ns.hi = log(T_i);                      // G(T_i) >= 0
+        ns.hi = flog(T_i);                     // G(T_i) >= 0
         if (T_e < T_floor && T_floor < T_i) {
           // the floor lies inside the bracket: probe it with cooling off first
           ns.kind = PROBE_OFF; ns.se = sf; ns.xe = T_floor; ns.flags &= ~F_ON;
@@ -603,7 +603,7 @@ struct CellSolver {
           ns.kind = PROBE_ON; ns.se = sf; ns.xe = T_floor; ns.flags |= F_ON;
         }
       } else if (Ge > 0.0) {                   // descent continues under the floor
-        ns.hi = sf; ns.lo = log(T_i); ns.flags |= F_LO_KNOWN;
+        ns.hi = sf; ns.lo = flog(T_i); ns.flags |= F_LO_KNOWN;
         ns.s = sf; ns.G = Ge; ns.dG = dGe; ns.z = ze; dzdx = dzdx_e;
         propose = true;
       } else {

@@ -62,10 +62,15 @@ def test_solver_elementary_functions():
     # powers of two and e^0 are exact
     k = np.arange(-1000, 1001, dtype=np.float64)
     assert np.array_equal(R.selftest_special_host(9, k), np.exp2(k))
-    # outside |s| < 700 exp takes the library path: overflow, underflow, inf, NaN
-    e = np.array([-np.inf, np.inf, 800.0, -800.0, 709.5])
+    # the ends of the range: the largest finite results, overflow, gradual
+    # underflow (to within the spacing of the smallest subnormal), inf, NaN
+    top = np.array([709.0, 709.5, 709.78])
+    assert _ulps(R.selftest_special_host(8, top), np.exp(top)) <= 2
+    e = np.array([-np.inf, np.inf, 800.0, -800.0, 709.8, 745.2, -746.0])
     with np.errstate(over="ignore"):
         assert np.array_equal(R.selftest_special_host(8, e), np.exp(e))
+    sub = np.array([-710.0, -720.0, -740.0, -744.0])
+    assert np.all(np.abs(R.selftest_special_host(8, sub) - np.exp(sub)) <= 5e-324)
     assert np.isnan(R.selftest_special_host(8, np.array([np.nan])))[0]
 
 
