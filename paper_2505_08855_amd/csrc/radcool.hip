@@ -208,6 +208,8 @@ void fill_geom(rc_tables_s* t) {
   for (int k = 0; k < 4; ++k)
     for (int j = 0; j < 4; ++j) t->geom.coef[k][j] = t->coef[k][j];
   for (int j = 0; j < 4; ++j) t->geom.coef_se[j] = t->coef[1][j] + t->coef[2][j];
+  const AxisP &a = t->geom.ax[1], &b = t->geom.ax[4];
+  t->geom.same_te = a.lo == b.lo && a.inv_d == b.inv_d && a.n == b.n;
 }
 
 rc_status upload(rc_tables_s* t, void* stream) {

@@ -71,6 +71,7 @@ struct TableGeom {
   AxisP ax[6];          // cooling (N, T_e, B), Coulomb (n_e, T_e, T_i)
   double coef[4][4];    // affine part of each log2 table in node-index space
   double coef_se[4];    // coef[1] + coef[2]: the synchrotron and eta tables enter as a sum
+  int same_te;          // the cooling and Coulomb T_e axes coincide (one coordinate serves both)
 };
 
 // Everything a step kernel needs besides the table memory.
@@ -455,7 +456,7 @@ struct CellSolver {
     const double lx = s * (1.0 / kLn10);
     double q, dq, dzdx;
     const Coord cT = axis_coord(lx, P.g->ax[1]);
-    const Coord ce = axis_coord(lx, P.g->ax[4]);
+    const Coord ce = P.g->same_te ? cT : axis_coord(lx, P.g->ax[4]);
     const double z0 = fmin(fmax(*z, fmin(x, T_i)), fmax(x, T_i));
     const Coord ci = axis_coord(flog10(z0), P.g->ax[5]);
     gather(cT, ce, ci, on);
@@ -669,8 +670,10 @@ struct CellSolver {
         // cells.
         const double zn = ns.z + dzdx * (xn - ns.xe);
         const double lxn = sn * (1.0 / kLn10);
-        const bool same_cells = (!(ns.flags & F_ON) || axis_coord(lxn, P.g->ax[1]).i == iT) &&
-                                axis_coord(lxn, P.g->ax[4]).i == ie && axis_coord(flog10(zn), P.g->ax[5]).i == ii;
+        const int jT = axis_coord(lxn, P.g->ax[1]).i;
+        const int je = P.g->same_te ? jT : axis_coord(lxn, P.g->ax[4]).i;
+        const bool same_cells = (!(ns.flags & F_ON) || jT == iT) && je == ie &&
+                                axis_coord(flog10(zn), P.g->ax[5]).i == ii;
         if (same_cells) {
           ns.z = zn;
           ns.kind = DONE; ns.xe = xn;
