@@ -434,7 +434,8 @@ typedef struct {
  * gradients the call keeps device scratch in the table handle: per-point
  * records, their keys and their bucket placement (about 200 bytes per cell)
  * plus 24 doubles per table cell, allocated
- * (hipMalloc) on the first call and whenever n grows past what it holds;
+ * (hipMalloc) on the first call and whenever n grows past what it holds
+ * (n up to 2^31 - 1 with table gradients: record positions are 32-bit);
  * backward calls with table gradients that overlap on one table handle must
  * therefore use the same stream.  Asynchronous on stream. */
 rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, int64_t n, double dt,

@@ -408,8 +408,10 @@ extern "C" rc_status rc_cool_step_backward(rc_tables t, const rc_state* state, i
   const long mc = (long)(ca.n[0] - 1) * (ca.n[1] - 1) * (ca.n[2] - 1);   // table cells
   const long mk = (long)(ka.n[0] - 1) * (ka.n[1] - 1) * (ka.n[2] - 1);
   const long nrec = 2 * n;                                               // records per table kind
-  if (nrec > 0xfffffffeLL) return set_error(RC_EINVAL, "rc_cool_step_backward: n too large for the gradient records");
   if (a.o_tab) {
+    // record positions are 32-bit
+    if (nrec > 0xfffffffeLL)
+      return set_error(RC_EINVAL, "rc_cool_step_backward: n too large for the table-gradient records");
     // buckets of each kind (cells per bucket, bucket count), workgroups of the count and placement passes
     const long cpb_c = cells_per_bucket<true>(mc), cpb_k = cells_per_bucket<false>(mk);
     const long nbc = (mc + cpb_c - 1) / cpb_c, nbk = (mk + cpb_k - 1) / cpb_k;

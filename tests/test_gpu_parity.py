@@ -217,6 +217,35 @@ def test_bad_arguments_raise(dev, imported64, cells0):
         R.cool_step(gt, st, DT, R.default_opts(block=100))
 
 
+def test_sizes_beyond_one_launch_are_refused(dev, imported64, cells0):
+    """A cell count whose grid exceeds one launch is refused on the host
+    (RC_EINVAL) before anything is launched or allocated, for the step in
+    every scheme and for the adjoint; the tensors behind the pointers hold 16
+    cells, so a launch would read far out of bounds (none happens)."""
+    import ctypes
+    gt, _ = imported64
+    st = to_dev(cells0, dev, np.arange(16))
+    out = R.cool_step(gt, st, DT)
+    L = R.lib()
+    s = R._state(st)
+    o = R._out_struct(out)
+    huge = 1 << 40
+    for kw in (dict(), dict(scheme="rates"), dict(scheme="explicit16"), dict(passes=2), dict(variant="global")):
+        opts = R.default_opts(**kw)
+        assert L.rc_cool_step(gt.handle, ctypes.byref(s), huge, DT, ctypes.byref(opts), ctypes.byref(o), None) == -1
+        assert b"too large" in L.rc_last_error(), kw
+    fwd = R.Fwd(out["T_e_new"].data_ptr(), out["T_i_new"].data_ptr(), out["status"].data_ptr())
+    cot = R.Cotangent(out["T_e_new"].data_ptr(), None, None, None)
+    g = R.Grad(*[out["T_e_new"].data_ptr()] * 5, None)
+    assert L.rc_cool_step_backward(gt.handle, ctypes.byref(s), huge, DT, ctypes.byref(R.default_opts()),
+                                   ctypes.byref(fwd), ctypes.byref(cot), ctypes.byref(g), None) == -1
+    assert b"too large" in L.rc_last_error()
+    torch.cuda.synchronize()
+    # the library still works
+    again = R.cool_step(gt, st, DT)
+    assert torch.equal(again["T_e_new"], out["T_e_new"])
+
+
 def test_deterministic(dev, imported64, cells0):
     gt, _ = imported64
     st = to_dev(cells0, dev)
