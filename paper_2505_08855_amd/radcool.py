@@ -350,10 +350,6 @@ def _check_out(out, n, opts):
     return out
 
 
-def _ptr(t):
-    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()
-
-
 def _check_state(state):
     import torch
     ref = state["n_e"]
