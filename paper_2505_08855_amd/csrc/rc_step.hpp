@@ -256,6 +256,7 @@ struct CellSolver {
   double K0, v00, v10, v01, v11;
   unsigned char clamp;
   bool cool_off;        // radiative cooling switched off for this cell (gas-temperature floor)
+  double lnTi;          // ln T_i; read only where the solve starts (newton_begin)
 
   RC_HD CellSolver(const Tab& t, const StepParams& p) : tab(t), P(p) {}
 
@@ -283,9 +284,10 @@ struct CellSolver {
     in_ = cn.i; tn = cn.t;
     const double s0 = flog(te);
     const double lte = s0 * (1.0 / kLn10);
+    lnTi = flog(ti);
     clamp = cool_off ? ST_GAS_FLOOR : 0;
     if (cN.clamped || cB.clamped || axis_coord(lte, P.g->ax[1]).clamped) clamp |= ST_CLAMP_COOL;
-    if (cn.clamped || axis_coord(lte, P.g->ax[4]).clamped || axis_coord(flog10(ti), P.g->ax[5]).clamped)
+    if (cn.clamped || axis_coord(lte, P.g->ax[4]).clamped || axis_coord(lnTi * kInvLn10, P.g->ax[5]).clamped)
       clamp |= ST_CLAMP_COUL;
     iT = ie = ii = -1;
     return s0;
@@ -409,16 +411,32 @@ struct CellSolver {
       K = it == 0 ? kcoul_at(ce, ci0, &dlx, &dlz) : kcoul(ce, z, &dlx, &dlz);
       if (it == 0 && K_first) *K_first = K;
       const double E = c * (z - T_i) + dt * (z - x) * K;
-      dEz = c + dt * K + dt * (z - x) * K * fdiv_d(dlz, z);
+      const double iz = fdiv_d(1.0, z);
+      const double Kz = K * dlz * iz;         // d v_c / dz
+      dEz = c + dt * K + dt * (z - x) * Kz;
       if (E == 0.0) break;                  // z is an exact root
       if (E < 0.0) lo = z; else hi = z;
-      const double dz = -fdiv_d(E, dEz);
-      // converged: Newton converges quadratically, so after a step below
-      // 1e-6 z the remaining error is of order 1e-12 z (on the iid cells the
-      // solution moves by at most 2.5e-14 against a 1e-8 threshold, which
-      // costs 15 % more inner evaluations).  Tested before the bracket
+      // Halley's step.  Inside one Coulomb cell ln v_c is linear in ln z
+      // (the interpolant is bilinear in the log coordinates), so
+      // v_c'' = v_c' (dlz - 1) / z and E2'' = dt (2 v_c' + (z - x) v_c'')
+      // exactly; the step is the Newton step divided by
+      // 1 - E2 E2'' / (2 E2'^2), kept as Newton's where that factor is below
+      // one half (strong curvature: the bracket then decides).
+      const double iE = fdiv_d(1.0, dEz);
+      const double r = E * iE;
+      const double d2E = dt * Kz * (2.0 + (z - x) * (dlz - 1.0) * iz);
+      const double h = 1.0 - 0.5 * r * d2E * iE;
+      const double dz = h > 0.5 ? -fdiv_d(r, h) : -r;
+      // converged: Halley's iteration converges cubically, so after a step
+      // below 1e-4 z the remaining error is of order 1e-12 z (a host count
+      // over 262,144 iid cells against Newton's iteration stopped at 1e-6 z:
+      // 8.01 instead of 9.53 inner passes per wavefront, T_e' moving by at
+      // most 1.5e-12 and T_i' by 2e-14, the largest distance from the
+      // oracle's solution unchanged at 1.2e-11).  A last step that crosses into another
+      // Coulomb cell leaves z outside the cell the solve evaluated, which the
+      // outer convergence test rejects.  Tested before the bracket
       // safeguard, which would reject a step below the bracket end's ulp.
-      if (fabs(dz) <= 1e-6 * z) { z += dz; break; }
+      if (fabs(dz) <= 1e-4 * z) { z += dz; break; }
       double zn = z + dz;
       if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
       z = zn;
@@ -451,14 +469,19 @@ struct CellSolver {
   //    cells and over the spherical profile: 5 and 4 model steps give the same
   //    round counts as 1 and 2, so the model's own root need not be reached.)
   static constexpr int kHeatSteps = 1, kCoolSteps = 2;
-  RC_HD double outer(double s, double x, bool on, int mode, double* z, double* dG, double* q_out,
-                     double* K_first, double* dzdx_out, double* ds3) {
+  RC_HD double outer(double s, double x, bool on, int mode, double lnTi_first, double* z, double* dG,
+                     double* q_out, double* K_first, double* dzdx_out, double* ds3) {
     const double lx = s * (1.0 / kLn10);
     double q, dq, dzdx;
     const Coord cT = axis_coord(lx, P.g->ax[1]);
     const Coord ce = P.g->same_te ? cT : axis_coord(lx, P.g->ax[4]);
     const double z0 = fmin(fmax(*z, fmin(x, T_i)), fmax(x, T_i));
-    const Coord ci = axis_coord(flog10(z0), P.g->ax[5]);
+    // the first evaluation (x = T_e) starts the inner solve at z0 = T_i,
+    // whose logarithm the caller passes
+    double lz0;
+    if (mode == 2) lz0 = lnTi_first * kInvLn10;
+    else lz0 = flog10(z0);
+    const Coord ci = axis_coord(lz0, P.g->ax[5]);
     gather(cT, ce, ci, on);
     q_rad(x, cT, on, &q, &dq);
     *z = solve_z(x, ce, z0, ci, &dzdx, K_first);
@@ -530,7 +553,10 @@ struct CellSolver {
 
   RC_HD void newton_begin(double s0, NewtonState& ns) const {
     ns.s = s0; ns.G = 0.0; ns.dG = 1.0; ns.z = T_i;
-    ns.lo = 0.0; ns.hi = 0.0;
+    // until the first round sets the bracket, hi carries ln T_i: the first
+    // inner solve starts at z = T_i and the bracket ends are logarithms of
+    // T_i (or of the floor), so one logarithm serves all three
+    ns.lo = 0.0; ns.hi = lnTi;
     ns.z_floor = T_i;
     ns.kind = FIRST; ns.iters = 0;
     ns.se = s0; ns.xe = T_e;
@@ -554,7 +580,7 @@ struct CellSolver {
     }
     const int mode = kind == ITER ? 1 : kind == FIRST ? 2 : 0;
     double ze = ns.z, dGe, q, Kf, dzdx_e, ds3;
-    const double Ge = outer(ns.se, ns.xe, (ns.flags & F_ON) != 0, mode, &ze, &dGe, &q, &Kf, &dzdx_e, &ds3);
+    const double Ge = outer(ns.se, ns.xe, (ns.flags & F_ON) != 0, mode, ns.hi, &ze, &dGe, &q, &Kf, &dzdx_e, &ds3);
     bool propose = false;
     // dz/dx at the iterate when this round's evaluation became the iterate;
     // 0 otherwise (the next inner solve then starts from z unchanged)
@@ -566,15 +592,14 @@ struct CellSolver {
       if (ns.G == 0.0) { o->T_e_new = T_e; o->T_i_new = ze; return true; }
       const bool on0 = (ns.flags & F_ON) != 0;
       if (ns.G > 0.0) {
+        ns.lo = fmin(ns.hi, sf);               // ln min(T_i, T_floor)
         ns.hi = ns.s;
-        ns.lo = flog(fmin(T_i, T_floor));
         if (on0) ns.flags |= F_FLOOR_PENDING;
         else ns.flags |= F_LO_KNOWN;          // below the floor G(T_i) < 0 is guaranteed
         propose = true;
       } else {
         ns.flags |= F_HEATING | F_LO_KNOWN;
-        ns.lo = ns.s;
-        ns.hi = flog(T_i);                     // G(T_i) >= 0
+        ns.lo = ns.s;                          // hi = ln T_i: G(T_i) >= 0
         if (T_e < T_floor && T_floor < T_i) {
           // the floor lies inside the bracket: probe it with cooling off first
           ns.kind = PROBE_OFF; ns.se = sf; ns.xe = T_floor; ns.flags &= ~F_ON;
