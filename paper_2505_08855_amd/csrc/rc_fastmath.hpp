@@ -7,18 +7,23 @@
 // ones, so these versions use textbook reductions and short polynomials:
 //
 //   log:  x = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(f),
-//         f = (m - 1) / (m + 1), |f| <= 0.1716, summed as the atanh series
-//         f + f^3/3 + ... + f^21/21 (first omitted term below 2^-56 relative);
+//         f = (m - 1) / (m + 1), |f| <= 0.1716, s = f^2:
+//         2 atanh(f) = 2 f (1 + s p(s)), p(s) = 1/3 + s/5 + s^2/7 + ...
+//         economized to degree 6 in s;
 //         e ln 2 with ln 2 split into a 21-bit head (exact products) and tail.
 //   exp2: y = k + f with k = rint(y), |f| <= 1/2; 2^f by its Taylor series in
-//         f (coefficients (ln 2)^j / j!, j <= 13; first omitted term < 2^-57).
+//         f (coefficients (ln 2)^j / j!) economized to degree 11.
 //   exp:  s = k ln 2 + r (Cody-Waite: k ln2_head exact), |r| <= 0.347,
-//         e^r by its Taylor series to r^13 / 13!, scaled by 2^k.
+//         e^r by its Taylor series economized to degree 11, scaled by 2^k.
 //   log1p: u = 1 + v, log1p(v) = ln(u) v / (u - 1) (Goldberg's correction
 //         for the rounding of 1 + v; exact when u == 1).
 //
-// Accuracy is a few ulp over the whole double range; the library's host
-// self-test compares every function with the C library.
+// The polynomials are Chebyshev economizations of the Taylor series over
+// the reduced ranges (fastmath_coeffs.py next to this file derives them in
+// exact arithmetic): two to three fused multiply-adds fewer than the
+// truncated series of the same accuracy.  Accuracy is a few ulp over the
+// whole double range; the library's host self-test compares every function
+// with the C library.
 #pragma once
 
 #include "rc_physics.hpp"
@@ -131,16 +136,13 @@ RC_HD double flog(double x) {
   }
   const double f = fdiv(m - 1.0, m + 1.0);   // m - 1 is exact
   const double s = f * f;
-  double p = 1.0 / 21.0;
-  p = hfma(p, s, 1.0 / 19.0);
-  p = hfma(p, s, 1.0 / 17.0);
-  p = hfma(p, s, 1.0 / 15.0);
-  p = hfma(p, s, 1.0 / 13.0);
-  p = hfma(p, s, 1.0 / 11.0);
-  p = hfma(p, s, 1.0 / 9.0);
-  p = hfma(p, s, 1.0 / 7.0);
-  p = hfma(p, s, 1.0 / 5.0);
-  p = hfma(p, s, 1.0 / 3.0);
+  double p = 0x1.2b62ca3da2e33p-4;
+  p = hfma(p, s, 0x1.39fd807189bb6p-4);
+  p = hfma(p, s, 0x1.7462bba41c635p-4);
+  p = hfma(p, s, 0x1.c71c62cbfea3fp-4);
+  p = hfma(p, s, 0x1.2492492e0644ep-3);   // ~1/7
+  p = hfma(p, s, 0x1.9999999995219p-3);   // ~1/5
+  p = hfma(p, s, 0x1.5555555555558p-2);   // ~1/3
   const double f2 = f + f;
   const double lm = fma(f2 * s, p, f2);    // 2 atanh f
   const double de = (double)e;
@@ -160,19 +162,17 @@ RC_HD double flog1p(double v) {
 RC_HD double fexp2(double y) {
   const double k = rint(y);
   const double f = y - k;             // exact
-  double p = 0x1.816193166d0f9p-40;   // (ln 2)^13 / 13!
-  p = hfma(p, f, 0x1.c3bd650fc2986p-36);
-  p = hfma(p, f, 0x1.e8cac7351bb25p-32);
-  p = hfma(p, f, 0x1.e4cf5158b8ecap-28);
-  p = hfma(p, f, 0x1.b5253d395e7c4p-24);
-  p = hfma(p, f, 0x1.62c0223a5c824p-20);
-  p = hfma(p, f, 0x1.ffcbfc588b0c7p-17);
-  p = hfma(p, f, 0x1.430912f86c787p-13);
-  p = hfma(p, f, 0x1.5d87fe78a6731p-10);
-  p = hfma(p, f, 0x1.3b2ab6fba4e77p-7);
-  p = hfma(p, f, 0x1.c6b08d704a0c0p-5);
-  p = hfma(p, f, 0x1.ebfbdff82c58fp-3);
-  p = hfma(p, f, 0x1.62e42fefa39efp-1);
+  double p = 0x1.ea044321bc0aap-32;   // ~(ln 2)^11 / 11!
+  p = hfma(p, f, 0x1.e6228bff026d1p-28);
+  p = hfma(p, f, 0x1.b524db38fd1f9p-24);
+  p = hfma(p, f, 0x1.62bfc2c7ae40ep-20);
+  p = hfma(p, f, 0x1.ffcbfc75f302dp-17);
+  p = hfma(p, f, 0x1.430913112cb56p-13);
+  p = hfma(p, f, 0x1.5d87fe78a2292p-10);
+  p = hfma(p, f, 0x1.3b2ab6fb9f1a3p-7);
+  p = hfma(p, f, 0x1.c6b08d704a0d1p-5);
+  p = hfma(p, f, 0x1.ebfbdff82c5aep-3);
+  p = hfma(p, f, 0x1.62e42fefa39efp-1);   // ln 2
   p = hfma(p, f, 1.0);
   return ldexp(p, (int)k);
 }
@@ -186,18 +186,16 @@ RC_HD double fexp(double s) {
   if (!(fabs(s) < 746.0)) return s > 0.0 ? __builtin_inf() : (s < 0.0 ? 0.0 : s);
   const double k = rint(s * kLog2E);
   const double r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, s));
-  double p = 1.0 / 6227020800.0;      // 1 / 13!
-  p = hfma(p, r, 1.0 / 479001600.0);
-  p = hfma(p, r, 1.0 / 39916800.0);
-  p = hfma(p, r, 1.0 / 3628800.0);
-  p = hfma(p, r, 1.0 / 362880.0);
-  p = hfma(p, r, 1.0 / 40320.0);
-  p = hfma(p, r, 1.0 / 5040.0);
-  p = hfma(p, r, 1.0 / 720.0);
-  p = hfma(p, r, 1.0 / 120.0);
-  p = hfma(p, r, 1.0 / 24.0);
-  p = hfma(p, r, 1.0 / 6.0);
-  p = hfma(p, r, 0.5);
+  double p = 0x1.af79f6e31795fp-26;   // ~1 / 11!
+  p = hfma(p, r, 0x1.28b538eba9034p-22);
+  p = hfma(p, r, 0x1.71dde673efb0ep-19);
+  p = hfma(p, r, 0x1.a019905f26df8p-16);
+  p = hfma(p, r, 0x1.a01a01b86d2fbp-13);
+  p = hfma(p, r, 0x1.6c16c18878da9p-10);
+  p = hfma(p, r, 0x1.111111110da35p-7);
+  p = hfma(p, r, 0x1.555555554ee74p-5);
+  p = hfma(p, r, 0x1.5555555555563p-3);
+  p = hfma(p, r, 0x1.0000000000011p-1);
   p = hfma(p, r, 1.0);
   p = hfma(p, r, 1.0);
   return ldexp(p, (int)k);

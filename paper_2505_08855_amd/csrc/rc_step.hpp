@@ -251,9 +251,10 @@ struct CellSolver {
   // cooling cache inside T cell iT: log2 v_brem = Ab + Sb t, log2(v_synch v_eta) = Ase + Sse t
   int iT;
   double Ab, Ase, Sb, Sse;
-  // Coulomb cache inside cell (ie, ii): log2 v_c = K0 + c2 te + c3 ti + bilinear(v00, v10, v01, v11)
+  // Coulomb cache inside cell (ie, ii): log2 v_c = C0 + C1 te + C2 ti + C3 te ti
+  // (the affine part plus the bilinear interpolant, expanded in te and ti)
   int ie, ii;
-  double K0, v00, v10, v01, v11;
+  double C0, C1, C2, C3;
   unsigned char clamp;
   bool cool_off;        // radiative cooling switched off for this cell (gas-temperature floor)
   double lnTi;          // ln T_i; read only where the solve starts (newton_begin)
@@ -329,12 +330,15 @@ struct CellSolver {
     const double w0 = 1.0 - tn, w1 = tn;
     float v[8];
     tab.coul8(in_, je, ji, v);
-    v00 = w0 * v[0] + w1 * v[4];
-    v10 = w0 * v[2] + w1 * v[6];
-    v01 = w0 * v[1] + w1 * v[5];
-    v11 = w0 * v[3] + w1 * v[7];
+    const double v00 = w0 * v[0] + w1 * v[4];
+    const double v10 = w0 * v[2] + w1 * v[6];
+    const double v01 = w0 * v[1] + w1 * v[5];
+    const double v11 = w0 * v[3] + w1 * v[7];
     const double* co = P.g->coef[3];
-    K0 = co[0] + co[1] * (in_ + tn) + co[2] * (double)je + co[3] * (double)ji;
+    C0 = co[0] + co[1] * (in_ + tn) + co[2] * (double)je + co[3] * (double)ji + v00;
+    C1 = co[2] + (v10 - v00);
+    C2 = co[3] + (v01 - v00);
+    C3 = (v11 - v10) - (v01 - v00);
   }
 
   // Corner gathers of one evaluation at T_e = x (cooling coordinate cT,
@@ -374,11 +378,9 @@ struct CellSolver {
   // gathered) and the partial derivatives d ln v_c / d ln T_e, d ln v_c / d ln T_i
   RC_HD double kcoul_at(const Coord& ce, const Coord& ci, double* dlx, double* dlz) const {
     const double te = ce.t, ti = ci.t;
-    const double c2 = P.g->coef[3][2], c3 = P.g->coef[3][3];
-    const double y = K0 + c2 * te + c3 * ti + (1.0 - te) * (1.0 - ti) * v00 + te * (1.0 - ti) * v10 +
-                     (1.0 - te) * ti * v01 + te * ti * v11;
-    const double dye = c2 + (1.0 - ti) * (v10 - v00) + ti * (v11 - v01);
-    const double dyi = c3 + (1.0 - te) * (v01 - v00) + te * (v11 - v10);
+    const double dye = C1 + C3 * ti;          // d log2 v_c / d te
+    const double dyi = C2 + C3 * te;          // d log2 v_c / d ti
+    const double y = C0 + C1 * te + dyi * ti;
     *dlx = kLn2 * dye * ce.dfdu * (1.0 / kLn10);
     *dlz = kLn2 * dyi * ci.dfdu * (1.0 / kLn10);
     return fexp2(y);
@@ -416,26 +418,29 @@ struct CellSolver {
       dEz = c + dt * K + dt * (z - x) * Kz;
       if (E == 0.0) break;                  // z is an exact root
       if (E < 0.0) lo = z; else hi = z;
-      // Halley's step.  Inside one Coulomb cell ln v_c is linear in ln z
-      // (the interpolant is bilinear in the log coordinates), so
-      // v_c'' = v_c' (dlz - 1) / z and E2'' = dt (2 v_c' + (z - x) v_c'')
-      // exactly; the step is the Newton step divided by
-      // 1 - E2 E2'' / (2 E2'^2), kept as Newton's where that factor is below
-      // one half (strong curvature: the bracket then decides).
+      // Chebyshev's third-order step.  Inside one Coulomb cell ln v_c is
+      // linear in ln z (the interpolant is bilinear in the log coordinates),
+      // so v_c'' = v_c' (dlz - 1) / z and E2'' = dt (2 v_c' + (z - x) v_c'')
+      // exactly; with the Newton step -r, r = E2 / E2', the step is
+      // -r (1 + r E2'' / (2 E2')), kept as Newton's where that correction
+      // exceeds one half (strong curvature: the bracket then decides).
+      // (Halley's form, -r / (1 - r E2'' / (2 E2')), takes the same number
+      // of passes and one division more.)
       const double iE = fdiv_d(1.0, dEz);
       const double r = E * iE;
       const double d2E = dt * Kz * (2.0 + (z - x) * (dlz - 1.0) * iz);
-      const double h = 1.0 - 0.5 * r * d2E * iE;
-      const double dz = h > 0.5 ? -fdiv_d(r, h) : -r;
-      // converged: Halley's iteration converges cubically, so after a step
-      // below 1e-4 z the remaining error is of order 1e-12 z (a host count
-      // over 262,144 iid cells against Newton's iteration stopped at 1e-6 z:
+      const double a = 0.5 * r * d2E * iE;
+      const double dz = fabs(a) < 0.5 ? -r * (1.0 + a) : -r;
+      // converged: the iteration converges cubically, so after a step below
+      // 1e-4 z the remaining error is of order 1e-12 z (a host count over
+      // 262,144 iid cells against Newton's iteration stopped at 1e-6 z:
       // 8.01 instead of 9.53 inner passes per wavefront, T_e' moving by at
       // most 1.5e-12 and T_i' by 2e-14, the largest distance from the
-      // oracle's solution unchanged at 1.2e-11).  A last step that crosses into another
-      // Coulomb cell leaves z outside the cell the solve evaluated, which the
-      // outer convergence test rejects.  Tested before the bracket
-      // safeguard, which would reject a step below the bracket end's ulp.
+      // oracle's solution unchanged at 1.2e-11).  A last step that crosses
+      // into another Coulomb cell leaves z outside the cell the solve
+      // evaluated, which the outer convergence test rejects.  Tested before
+      // the bracket safeguard, which would reject a step below the bracket
+      // end's ulp.
       if (fabs(dz) <= 1e-4 * z) { z += dz; break; }
       double zn = z + dz;
       if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
