@@ -20,10 +20,11 @@ namespace rc {
 // Occupancy target (waves per SIMD) the register allocator works to for
 // each scheme; the Newton solve trades a little spilling for latency hiding.
 // Measured on the 256^3 iid step (128^3 tables): the one-kernel solve at 3
-// waves per SIMD (168 VGPRs, about 30 spilled) 2.79 ms against 3.20 ms at 2
-// (no spills); the two-pass step 2.88 ms with its first pass at 2 and its
-// resumed pass at 3 (the first pass spills 29 registers at 3).  The solve is
-// bound by table-gather latency more than by issue, so occupancy pays.
+// waves per SIMD (168 VGPRs, 6 spilled) 2.18 ms against 2.67 ms at 2 (182
+// VGPRs, none spilled) and 2.84 ms at 4 (128 VGPRs, 52 spilled); the
+// two-pass step keeps its first pass at 2 and its resumed pass at 3.  Three
+// waves hide the table-gather and transcendental latencies well enough; a
+// fourth costs more in spill traffic than it hides.
 #ifndef RC_NEWTON_WAVES
 #define RC_NEWTON_WAVES 3
 #endif
