@@ -74,6 +74,65 @@ def test_solver_elementary_functions():
     assert np.isnan(R.selftest_special_host(8, np.array([np.nan])))[0]
 
 
+def _fastmath_generator():
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(R.__file__), "csrc", "fastmath_coeffs.py")
+    spec = importlib.util.spec_from_file_location("fastmath_coeffs", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_polynomial_coefficients_are_the_economized_series():
+    """The polynomial coefficients in rc_fastmath.hpp are the ones the
+    committed generator derives, and each economized polynomial stays within
+    2^-55 of its function over the reduced range (exact rational arithmetic
+    against the Taylor series to degree 30, whose own remainder is below
+    1e-30 there)."""
+    import math
+    import os
+    import re
+    from fractions import Fraction as F
+    gen = _fastmath_generator()
+    tabs = gen.tables()
+    src = open(os.path.join(os.path.dirname(R.__file__), "csrc", "rc_fastmath.hpp")).read()
+
+    def body(name):
+        i = src.index(name)
+        return src[i:src.index("\n}\n", i)]
+
+    def coeffs(text):
+        return [float.fromhex(h) for h in re.findall(r"(0x1\.[0-9a-f]+p[-+]\d+)", text)]
+
+    # constants of each function, highest degree first (1.0 terms are written as literals)
+    assert coeffs(body("RC_HD double fexp2(")) == [float(c) for c in tabs["exp2"][::-1][:-1]]
+    assert coeffs(body("RC_HD double fexp(")) == [float(c) for c in tabs["exp"][::-1][:-2]]
+    assert coeffs(body("RC_HD double flog(")) == [float(c) for c in tabs["atanh p"][::-1]]
+    assert float(tabs["exp2"][0]) == 1.0 and float(tabs["exp"][0]) == float(tabs["exp"][1]) == 1.0
+
+    def horner(c, x):
+        p = F(0)
+        for a in c[::-1]:
+            p = p * x + F(float(a))          # the coefficients as stored
+        return p
+
+    ln2 = gen.LN2
+    for k in range(-32, 33):
+        f = F(k, 64)
+        ref = sum(ln2 ** j * f ** j / math.factorial(j) for j in range(31))
+        assert abs(horner(tabs["exp2"], f) - ref) / ref < F(1, 2 ** 55)
+        r = f * ln2 * F(1002, 1000)
+        ref = sum(r ** j / math.factorial(j) for j in range(31))
+        assert abs(horner(tabs["exp"], r) - ref) / ref < F(1, 2 ** 55)
+    smax = ((gen.SQRT2 - 1) / (gen.SQRT2 + 1)) ** 2
+    for k in range(0, 33):
+        sv = smax * F(k, 32)
+        ref = sum(sv ** j / (2 * j + 3) for j in range(31))
+        # p enters ln m = 2 f (1 + s p(s)): its error counts times s
+        assert abs(horner(tabs["atanh p"], sv) - ref) * sv < F(1, 2 ** 55)
+
+
 @pytest.mark.parametrize("n", [64, 128])
 def test_node_values_match_oracle(n):
     spec = R.default_spec(n)
