@@ -237,6 +237,13 @@ RC_HD FixedCoords fixed_coords(const StepParams& P, double n_e, double b, double
   return {axis_coord(lne + lh, P.g->ax[0]), axis_coord(flog10(b), P.g->ax[2]), axis_coord(lne, P.g->ax[3])};
 }
 
+// The inner solve's last evaluation point: its T_i coordinate t (with the
+// clamp flag) and 1 / z there.
+struct ZLast {
+  double t, iz;
+  bool clamped;
+};
+
 template <class Tab>
 struct CellSolver {
   const Tab& tab;
@@ -387,33 +394,39 @@ struct CellSolver {
   }
 
   // the same at T_i = z, gathering the Coulomb cell if z left the cached one
-  RC_HD double kcoul(const Coord& ce, double z, double* dlx, double* dlz) {
+  RC_HD double kcoul(const Coord& ce, double z, double* dlx, double* dlz, Coord* ci_out) {
     const Coord ci = axis_coord(flog10(z), P.g->ax[5]);
     if (ce.i != ie || ci.i != ii) load_coul(ce.i, ci.i);
+    *ci_out = ci;
     return kcoul_at(ce, ci, dlx, dlz);
   }
 
   // z(x) solving E2 = c (z - T_i) + dt (z - x) v_c(x, z) = 0 inside
   // [min(x, T_i), max(x, T_i)], where E2 changes sign; returns z and dz/dx.
   // z0 is the first trial z, already inside that interval, with its Coulomb
-  // coordinate ci0 (cell gathered); *K_first receives v_c there.
-  RC_HD double solve_z(double x, const Coord& ce, double z0, const Coord& ci0, double* dzdx, double* K_first) {
+  // coordinate ci0 (cell gathered); *K_first receives v_c there.  *zl
+  // receives the last evaluation point's T_i coordinate and 1 / z there
+  // (the Coulomb cell cached on return is that point's).
+  RC_HD double solve_z(double x, const Coord& ce, double z0, const Coord& ci0, double* dzdx, double* K_first,
+                       ZLast* zl) {
     double lo = fmin(x, T_i), hi = fmax(x, T_i);
     double z = z0;
     double K = 0.0, dlx = 0.0, dlz = 0.0;
+    Coord cz = ci0;
     if (!(hi > lo)) {
       // x == T_i: z = T_i solves E2; implicit derivative dz/dx = dt K / (c + dt K)
       K = kcoul_at(ce, ci0, &dlx, &dlz);
       if (K_first) *K_first = K;
       *dzdx = fdiv_d(dt * K, c + dt * K);
+      zl->t = ci0.t; zl->iz = fdiv_d(1.0, lo); zl->clamped = ci0.clamped;
       return lo;
     }
-    double dEz = c;
+    double dEz = c, iz = 0.0;
     for (int it = 0; it < 60; ++it) {
-      K = it == 0 ? kcoul_at(ce, ci0, &dlx, &dlz) : kcoul(ce, z, &dlx, &dlz);
+      K = it == 0 ? kcoul_at(ce, ci0, &dlx, &dlz) : kcoul(ce, z, &dlx, &dlz, &cz);
       if (it == 0 && K_first) *K_first = K;
       const double E = c * (z - T_i) + dt * (z - x) * K;
-      const double iz = fdiv_d(1.0, z);
+      iz = fdiv_d(1.0, z);
       const double Kz = K * dlz * iz;         // d v_c / dz
       dEz = c + dt * K + dt * (z - x) * Kz;
       if (E == 0.0) break;                  // z is an exact root
@@ -449,6 +462,7 @@ struct CellSolver {
     }
     const double dEx = -dt * K + dt * (z - x) * K * fdiv_d(dlx, x);
     *dzdx = -fdiv_d(dEx, dEz);
+    zl->t = cz.t; zl->iz = iz; zl->clamped = cz.clamped;
     return z;
   }
 
@@ -475,7 +489,7 @@ struct CellSolver {
   //    round counts as 1 and 2, so the model's own root need not be reached.)
   static constexpr int kHeatSteps = 1, kCoolSteps = 2;
   RC_HD double outer(double s, double x, bool on, int mode, double lnTi_first, double* z, double* dG,
-                     double* q_out, double* K_first, double* dzdx_out, double* ds3) {
+                     double* q_out, double* K_first, double* dzdx_out, double* ds3, ZLast* zl) {
     const double lx = s * (1.0 / kLn10);
     double q, dq, dzdx;
     const Coord cT = axis_coord(lx, P.g->ax[1]);
@@ -489,7 +503,7 @@ struct CellSolver {
     const Coord ci = axis_coord(lz0, P.g->ax[5]);
     gather(cT, ce, ci, on);
     q_rad(x, cT, on, &q, &dq);
-    *z = solve_z(x, ce, z0, ci, &dzdx, K_first);
+    *z = solve_z(x, ce, z0, ci, &dzdx, K_first, zl);
     const double numer = c * ((x - T_e) + (*z - T_i)) + dt * q;
     const double cx = c * x * (1.0 + dzdx);
     const double cS = c * (T_e + T_i);
@@ -585,7 +599,8 @@ struct CellSolver {
     }
     const int mode = kind == ITER ? 1 : kind == FIRST ? 2 : 0;
     double ze = ns.z, dGe, q, Kf, dzdx_e, ds3;
-    const double Ge = outer(ns.se, ns.xe, (ns.flags & F_ON) != 0, mode, ns.hi, &ze, &dGe, &q, &Kf, &dzdx_e, &ds3);
+    ZLast zl;
+    const double Ge = outer(ns.se, ns.xe, (ns.flags & F_ON) != 0, mode, ns.hi, &ze, &dGe, &q, &Kf, &dzdx_e, &ds3, &zl);
     bool propose = false;
     // dz/dx at the iterate when this round's evaluation became the iterate;
     // 0 otherwise (the next inner solve then starts from z unchanged)
@@ -702,8 +717,22 @@ struct CellSolver {
         const double lxn = sn * (1.0 / kLn10);
         const int jT = axis_coord(lxn, P.g->ax[1]).i;
         const int je = P.g->same_te ? jT : axis_coord(lxn, P.g->ax[4]).i;
-        const bool same_cells = (!(ns.flags & F_ON) || jT == iT) && je == ie &&
-                                axis_coord(flog10(zn), P.g->ax[5]).i == ii;
+        // T_i cell of zn against the cached one, from the last inner
+        // evaluation's coordinate t at z_l: with u = zn / z_l - 1 the new
+        // coordinate is t + (dt/d ln z) ln(1 + u), and u (1 + 2|u|) <=
+        // ln(1 + u) <= u for |u| <= 1/2, so the test is conservative (a
+        // point next to a cell edge may take one more round).  A clamped
+        // coordinate takes the exact test.
+        bool same_ti;
+        if (zl.clamped) {
+          same_ti = axis_coord(flog10(zn), P.g->ax[5]).i == ii;
+        } else {
+          const double u = fma(zn, zl.iz, -1.0);
+          const double au = fabs(u), dtdl = P.g->ax[5].inv_d * kInvLn10;
+          same_ti = au < 0.25 && zl.t + dtdl * fmin(u, 0.0) * (1.0 + 2.0 * au) >= 0.0 &&
+                    zl.t + dtdl * fmax(u, 0.0) < 1.0;
+        }
+        const bool same_cells = (!(ns.flags & F_ON) || jT == iT) && je == ie && same_ti;
         if (same_cells) {
           ns.z = zn;
           ns.kind = DONE; ns.xe = xn;
